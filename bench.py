@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Benchmark of the Chebyshev-Jacobi (CJM) FP64 Poisson solve on one MI355X.
+
+One step = one full solve through the C ABI (stage-in, cycles of weighted
+sweeps with the fused cycle-end residual test, stage-out) of the workload
+  8192 x 8192 interior nodes, 9-point stencil (alpha = 2/3), homogeneous
+  Dirichlet data, RHS = 16 seeded Gaussian bumps, tol = 1e-10 relative residual,
+with f already resident in HBM.  Prints one JSON line.
+
+value      = grid-point updates / s over the timed steps (updates = nx*ny*cycles*M)
+roofline   = the plain sweep kernel (the dominant one): algorithmic bytes per
+             launch (24 B per grid-point update: read u, read g, write u', FP64)
+             divided by its average launch duration, timed inside the library
+             with HIP events on the solve's stream, against 8 TB/s HBM.
+cpu_baseline = the CPU oracle's sweep loop on the same workload, for a bounded
+             number of sweeps (about --cpu-seconds of host time).
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "grid-point updates/s + time-to-tol (1e-10 rel resid); p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_UPDATE = 24.0   # FP64: u and g read, u' written
+KERNEL_SRC = os.path.join(ROOT, "paper_1705_00103_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep9_f64_8192_traffic.md")
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(n, stencil):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary, or
+    None when there is none or the kernel source changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    text = open(TRAFFIC_FILE).read()
+    m = re.search(r"kernels\.hip sha256\[:16\]:\s*([0-9a-f]{16})", text)
+    t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    w = re.search(r"workload:\s*n=(\d+)\s+stencil=(\d+)", text)
+    if not (m and t and w) or m.group(1) != kernel_hash():
+        return None
+    if int(w.group(1)) != n or int(w.group(2)) != stencil:
+        return None
+    return float(t.group(1))
+
+
+def cpu_baseline(f, n, stencil, tol, budget_s):
+    from oracle import cjm
+    import numpy as np
+    p = cjm.plan(n, n, stencil, tol)
+    a = cjm.pad(np.zeros((n, n)), n, n)
+    b = np.zeros_like(a)
+    k = 0
+    t0 = time.perf_counter()
+    while True:
+        cjm.sweep(p, f, a, b, p.weights[k % p.M])
+        a, b = b, a
+        k += 1
+        if k >= 2 and time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": n * n * k / dt, "unit": "grid-point updates/s", "cores": cjm.threads(),
+            "kind": "oracle",
+            "sample": "%d sweeps of the %dx%d %d-point schedule from u=0 (oracle sweep loop, FP64, "
+                      "OpenMP over rows), %.1f s" % (k, n, n, stencil, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=8192, help="interior nodes per axis")
+    ap.add_argument("--stencil", type=int, default=9, choices=(5, 9, 17))
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--seed", type=int, default=None, help="RHS seed (default 1705 + stencil)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+              "(a single solve is one GPU's work; see DESIGN.md for how it would shard)" % args.gpus,
+              file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1705_00103_amd import cj, inputs
+
+    n, st, tol = args.n, args.stencil, args.tol
+    seed = 1705 + st if args.seed is None else args.seed
+    f = inputs.gaussian_bumps_rhs(n, n, seed=seed)
+    fd = torch.from_numpy(f).to("cuda")
+    u = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+    p = cj.plan(n, n, st, tol)
+
+    for _ in range(args.warmup):
+        u.zero_()
+        cj.solve(p, fd, u)
+    torch.cuda.synchronize()
+
+    lat, res = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        u.zero_()
+        r = cj.solve(p, fd, u)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+        res.append(r)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+
+    ms_per_step = (t1 - t0) / args.steps * 1e3
+    updates_per_step = float(n) * n * sum(r["sweeps"] for r in res) / args.steps
+    value = updates_per_step / (ms_per_step * 1e-3)
+
+    sweep_s = sum(r["sweep_seconds"] for r in res)
+    launches = sum(r["sweep_launches"] for r in res)
+    roofline = None
+    if launches > 0:
+        avg = sweep_s / launches
+        algo = BYTES_PER_UPDATE * n * n
+        achieved = algo / avg / 1e9
+        traffic = measured_traffic(n, st)
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "kernel": "sweep_kernel<%d, write, no-norm>" % st,
+                    "avg_launch_us": round(avg * 1e6, 2), "algorithmic_bytes_per_launch": algo}
+
+    lat_ms = sorted(x * 1e3 for x in lat)
+    p50 = float(np.percentile(lat_ms, 50))
+    p99 = float(np.percentile(lat_ms, 99))
+    last = res[-1]
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(f, n, st, tol, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "cjm-fp64-%dpt-%dx%d-bumps16-tol%g" % (st, n, n, tol),
+            "nx": n, "ny": n, "stencil": st, "tol": tol, "rhs_seed": seed, "M": p.M,
+            "cycles_pred": p.cycles_pred, "parallelism": "single-gpu",
+        },
+        "time_to_tol_p50_ms": p50,
+        "time_to_tol_p99_ms": p99,
+        "solve_status": last["status"],
+        "cycles": last["cycles"],
+        "sweeps_per_solve": last["sweeps"],
+        "rel_residual": last["rel_residual"],
+        "effective_tol": last["rel_residual"] if last["status"] == "stagnated" else tol,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    if cpu is not None:
+        out["gpu_over_cpu_updates"] = value / cpu["value"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,152 @@
+/*
+ * cj.h -- C ABI of libcj.so, the Chebyshev-Jacobi method (CJM) for the 2D
+ * finite-difference Poisson problem on AMD Instinct MI355X (gfx950).
+ *
+ * The method (Adsuara et al., "Speeding up a few orders of magnitude the
+ * Jacobi method: high order Chebyshev-Jacobi over GPUs", §2.1): a weighted
+ * Jacobi iteration u <- u + omega_n D^{-1} (f - A u) whose weights omega_n are
+ * the reciprocals of the zeros of a Chebyshev polynomial mapped onto the
+ * interval [kappa_min, kappa_max] that bounds the spectrum of D^{-1} A.  The
+ * bounds are the paper's closed forms (§2.1, Eqs. for kappa^(9), kappa^(17);
+ * the 5-point bounds follow from the stencil symbol).  The weights are
+ * computed once per plan on the host in FP64 and applied in a fixed order.
+ *
+ * Problem.  nx x ny interior unknowns u(i, j), 1 <= i <= nx, 1 <= j <= ny, at
+ * x_i = i h, y_j = j h on a uniform mesh.  The paper's N_x, N_y (number of
+ * intervals) are nx + 1 and ny + 1; the default mesh spacing is
+ * h = 1 / max(nx + 1, ny + 1).  Homogeneous Dirichlet data on the boundary
+ * nodes i in {0, nx + 1}, j in {0, ny + 1}.  The system solved is A u = f
+ * with A = -Delta_h, Delta_h the chosen stencil (§2.1, Eq. "9-points" and
+ * Eq. "17-points"; Table "tab:ste2" for the classical 5-point stencil).  The
+ * 17-point stencil reaches one node beyond the boundary; that node holds the
+ * odd reflection of the interior (u(-1, j) = -u(1, j), likewise on every
+ * side), which keeps the sine modes exact eigenvectors.
+ *
+ * Arrays.  f and u are device pointers to nx*ny doubles, row-major with x
+ * fastest: element (i, j) at index (j - 1) * nx + (i - 1).  They must be
+ * 8-byte aligned.  The caller owns them; the library never frees them.
+ *
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the null
+ * stream).  All device work of a call is enqueued on that stream.  cj_solve,
+ * cj_sweeps, cj_residual and cj_apply return after that work has completed.
+ *
+ * Errors.  Every call returns a cj_status; nothing aborts or throws across
+ * the ABI.  cj_last_error() gives a message for the calling thread's last
+ * failure.  Device pointers are checked for NULL and alignment only.  A plan
+ * may be used by one thread at a time; separate plans are independent.
+ */
+#ifndef CJ_H
+#define CJ_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cj_plan_s* cj_plan_t;
+
+typedef enum {
+    CJ_OK = 0,                  /* converged: relative residual <= tol */
+    CJ_STAGNATED = 1,           /* stopped at the FP64 floor (see cj_solve) */
+    CJ_ERR_ARG = -1,            /* invalid argument */
+    CJ_ERR_NOMEM = -2,          /* device or host allocation failed */
+    CJ_ERR_HIP = -3,            /* a HIP runtime call failed */
+    CJ_ERR_NOT_CONVERGED = -4,  /* max_cycles reached above tol */
+    CJ_ERR_NONFINITE = -5,      /* NaN or Inf in f, u or the residual */
+    CJ_ERR_DEVICE = -6          /* plan used on a device other than its first */
+} cj_status;
+
+typedef enum { CJ_STENCIL_5 = 5, CJ_STENCIL_9 = 9, CJ_STENCIL_17 = 17 } cj_stencil;
+
+typedef enum { CJ_BC_DIRICHLET0 = 0 } cj_bc;
+
+/* Tuning and schedule options for cj_plan_ex.  Zero means "automatic". */
+typedef struct {
+    int    M;                  /* cycle length; 0 = the power of two 2^p that minimises
+                                  (predicted cycles x M), ties to the smaller; else a
+                                  power of two, 1 <= M <= 2^24 */
+    int    max_cycles;         /* 0 = predicted cycles + 4 */
+    int    sweeps_per_launch;  /* temporal-blocking depth k of the sweep kernels, 0 = auto */
+    int    tile_rows;          /* rows per workgroup tile of the sweep kernel, 0 = auto */
+    double h;                  /* mesh spacing; 0 = 1 / max(nx + 1, ny + 1) */
+    int    reserved[8];        /* must be zero */
+} cj_options;
+
+/* Outcome of a solve. */
+typedef struct {
+    int       status;          /* the cj_status returned */
+    int       cycles;          /* completed weight cycles */
+    long long sweeps;          /* cycles * M */
+    double    rel_residual;    /* ||f - A u||_2 / ||f||_2 of the returned u */
+    double    floor_estimate;  /* on CJ_STAGNATED: the residual level successive cycles
+                                  stopped improving on; 0 otherwise */
+    double    seconds;         /* host wall time of the call */
+    double    sweep_seconds;   /* device time of the plain sweep launches (those not fused
+                                  with the residual), timed with HIP events on `stream` */
+    long long sweep_launches;  /* number of launches sweep_seconds covers */
+} cj_result;
+
+/* Fills *opt with zeros (all automatic). */
+void cj_options_init(cj_options* opt);
+
+/* Builds a plan on the host (no device work): kappa_min/kappa_max from the
+ * closed forms with N = n + 1 (§2.1), the cycle length M, and the M weights
+ * omega_j = 2 / ((kmax + kmin) - (kmax - kmin) cos(theta_j pi / (2M))), with
+ * theta_j running over the odd integers 1 .. 2M - 1 in the recursive
+ * symmetric-pair order S_1 = [1], S_2m = [s_1, 4m - s_1, s_2, 4m - s_2, ...]
+ * (keeps every tail product of the cycle polynomial bounded by one).
+ * nx, ny >= 1; stencil in {5, 9, 17}; bc = CJ_BC_DIRICHLET0; tol > 0.
+ * On success *out owns the plan; release it with cj_plan_destroy. */
+cj_status cj_plan(int nx, int ny, int stencil, int bc, double tol, cj_plan_t* out);
+cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol,
+                     const cj_options* opt, cj_plan_t* out);
+
+/* Reads a plan.  Any output pointer may be NULL.  *weights_host points to the
+ * plan's M weights in applied order (owned by the plan, valid until destroy).
+ * *workspace_bytes is the device memory cj_solve allocates on first use:
+ * two padded iterates, the padded scaled right-hand side, the weights and
+ * the reduction buffers. */
+cj_status cj_plan_info(cj_plan_t p, double* kmin, double* kmax, int* M, int* cycles_pred,
+                       const double** weights_host, size_t* workspace_bytes);
+
+/* Solves A u = f.  u is read as the initial guess and overwritten with the
+ * solution.  Cycles of M sweeps are run; the relative residual
+ * ||f - A u||_2 / ||f||_2 is tested at cycle ends only (the paper stops at a
+ * prescribed tolerance, §3.4; mid-cycle iterates are not meaningful).  Stops
+ * with CJ_OK when it is <= tol; with CJ_STAGNATED when, at or after the
+ * predicted cycle count, a cycle fails to halve it (the FP64 floor of large
+ * grids); with CJ_ERR_NOT_CONVERGED after max_cycles.  In each of these cases
+ * u holds the last cycle-end iterate.  f = 0 gives u = 0 and CJ_OK.
+ * CJ_ERR_NONFINITE if f or an iterate has a NaN or Inf.  The device
+ * workspace is allocated on the first call and kept by the plan.
+ * res may be NULL. */
+cj_status cj_solve(cj_plan_t p, const double* f, double* u, void* stream, cj_result* res);
+
+/* Applies the first n_sweeps weighted sweeps of the plan's schedule (weights
+ * taken cyclically) to the guess u, with no residual test; u is overwritten.
+ * Same kernels and launch configuration as cj_solve.  n_sweeps >= 0. */
+cj_status cj_sweeps(cj_plan_t p, const double* f, double* u, long long n_sweeps, void* stream);
+
+/* *rel_residual = ||f - A u||_2 / ||f||_2 (0 when f = 0), FP64 with a
+ * deterministic reduction order. */
+cj_status cj_residual(cj_plan_t p, const double* f, const double* u, void* stream,
+                      double* rel_residual);
+
+/* au = A u = -Delta_h u (the stencil apply), same layout as u. */
+cj_status cj_apply(cj_plan_t p, const double* u, double* au, void* stream);
+
+/* Frees the plan and its device workspace.  NULL is ignored. */
+void cj_plan_destroy(cj_plan_t p);
+
+/* Static text for a status code. */
+const char* cj_status_string(int status);
+
+/* Message for the calling thread's last failed call ("" if none). */
+const char* cj_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CJ_H */

@@ -1,0 +1,207 @@
+"""Python binding of libcj.so (include/cj.h): argument marshalling only.
+
+Every computation runs in the library's HIP kernels.  Grids are torch tensors
+on the GPU: float64, contiguous, shape (ny, nx) (x fastest).  torch provides
+device memory and the current HIP stream; nothing else.
+
+    import torch
+    from paper_1705_00103_amd import cj
+    p = cj.plan(nx, ny, stencil=9, tol=1e-10)
+    u = torch.zeros(ny, nx, dtype=torch.float64, device="cuda")
+    res = cj.solve(p, f, u)        # u now holds the solution
+"""
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcj.so")
+
+CJ_OK = 0
+CJ_STAGNATED = 1
+CJ_ERR_ARG = -1
+CJ_ERR_NOMEM = -2
+CJ_ERR_HIP = -3
+CJ_ERR_NOT_CONVERGED = -4
+CJ_ERR_NONFINITE = -5
+CJ_ERR_DEVICE = -6
+
+STATUS_NAMES = {
+    CJ_OK: "ok", CJ_STAGNATED: "stagnated", CJ_ERR_ARG: "arg", CJ_ERR_NOMEM: "nomem",
+    CJ_ERR_HIP: "hip", CJ_ERR_NOT_CONVERGED: "not_converged", CJ_ERR_NONFINITE: "nonfinite",
+    CJ_ERR_DEVICE: "device",
+}
+
+# Function names declared in include/cj.h (checked against the header by the tests).
+EXPORTS = ("cj_options_init", "cj_plan", "cj_plan_ex", "cj_plan_info", "cj_solve", "cj_sweeps",
+           "cj_residual", "cj_apply", "cj_plan_destroy", "cj_status_string", "cj_last_error")
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int), ("max_cycles", ctypes.c_int),
+                ("sweeps_per_launch", ctypes.c_int), ("tile_rows", ctypes.c_int),
+                ("h", ctypes.c_double), ("reserved", ctypes.c_int * 8)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("cycles", ctypes.c_int), ("sweeps", ctypes.c_longlong),
+                ("rel_residual", ctypes.c_double), ("floor_estimate", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("sweep_seconds", ctypes.c_double),
+                ("sweep_launches", ctypes.c_longlong)]
+
+    def as_dict(self):
+        return dict(status=STATUS_NAMES.get(self.status, str(self.status)), code=self.status,
+                    cycles=self.cycles, sweeps=self.sweeps, rel_residual=self.rel_residual,
+                    floor_estimate=self.floor_estimate, seconds=self.seconds,
+                    sweep_seconds=self.sweep_seconds, sweep_launches=self.sweep_launches)
+
+
+class CJError(RuntimeError):
+    def __init__(self, code, where, msg):
+        super().__init__("%s failed: %s (%s)" % (where, STATUS_NAMES.get(code, code), msg))
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Loads libcj.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libcj.so is not built (%s); run __graft_entry__.build() or "
+                               "python -m paper_1705_00103_amd.build" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+        c_int, c_double = ctypes.c_int, ctypes.c_double
+        L.cj_options_init.argtypes = [ctypes.POINTER(Options)]
+        L.cj_options_init.restype = None
+        L.cj_plan.argtypes = [c_int, c_int, c_int, c_int, c_double, ctypes.POINTER(vp)]
+        L.cj_plan.restype = c_int
+        L.cj_plan_ex.argtypes = [c_int, c_int, c_int, c_int, c_double, ctypes.POINTER(Options),
+                                 ctypes.POINTER(vp)]
+        L.cj_plan_ex.restype = c_int
+        L.cj_plan_info.argtypes = [vp, dp, dp, ip, ip, ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_size_t)]
+        L.cj_plan_info.restype = c_int
+        L.cj_solve.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Result)]
+        L.cj_solve.restype = c_int
+        L.cj_sweeps.argtypes = [vp, vp, vp, ctypes.c_longlong, vp]
+        L.cj_sweeps.restype = c_int
+        L.cj_residual.argtypes = [vp, vp, vp, vp, dp]
+        L.cj_residual.restype = c_int
+        L.cj_apply.argtypes = [vp, vp, vp, vp]
+        L.cj_apply.restype = c_int
+        L.cj_plan_destroy.argtypes = [vp]
+        L.cj_plan_destroy.restype = None
+        L.cj_status_string.argtypes = [c_int]
+        L.cj_status_string.restype = ctypes.c_char_p
+        L.cj_last_error.argtypes = []
+        L.cj_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def last_error():
+    return lib().cj_last_error().decode()
+
+
+def status_string(code):
+    return lib().cj_status_string(code).decode()
+
+
+def _check(code, where, ok=(CJ_OK,)):
+    if code not in ok:
+        raise CJError(code, where, last_error())
+    return code
+
+
+class Plan:
+    """Owns a cj_plan_t.  Attributes mirror cj_plan_info."""
+
+    def __init__(self, nx, ny, stencil=9, tol=1e-10, M=0, max_cycles=0, sweeps_per_launch=0,
+                 tile_rows=0, h=0.0, bc=0):
+        L = lib()
+        o = Options()
+        L.cj_options_init(ctypes.byref(o))
+        o.M, o.max_cycles, o.sweeps_per_launch, o.tile_rows, o.h = M, max_cycles, sweeps_per_launch, tile_rows, h
+        handle = ctypes.c_void_p()
+        _check(L.cj_plan_ex(nx, ny, stencil, bc, tol, ctypes.byref(o), ctypes.byref(handle)), "cj_plan_ex")
+        self._h = handle
+        self.nx, self.ny, self.stencil, self.tol = nx, ny, stencil, tol
+        kmin, kmax = ctypes.c_double(), ctypes.c_double()
+        Mo, cp = ctypes.c_int(), ctypes.c_int()
+        w = ctypes.POINTER(ctypes.c_double)()
+        ws = ctypes.c_size_t()
+        _check(L.cj_plan_info(handle, ctypes.byref(kmin), ctypes.byref(kmax), ctypes.byref(Mo),
+                              ctypes.byref(cp), ctypes.byref(w), ctypes.byref(ws)), "cj_plan_info")
+        self.kmin, self.kmax, self.M, self.cycles_pred = kmin.value, kmax.value, Mo.value, cp.value
+        self.weights = [w[k] for k in range(self.M)]
+        self.workspace_bytes = ws.value
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("plan destroyed")
+        return self._h
+
+    def destroy(self):
+        if self._h is not None and _lib is not None:
+            _lib.cj_plan_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def plan(nx, ny, stencil=9, tol=1e-10, **opts):
+    return Plan(nx, ny, stencil, tol, **opts)
+
+
+def _grid_ptr(t, p, name, writable=False):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.device.type != "cuda" or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous float64 GPU tensor" % name)
+    if t.numel() != p.nx * p.ny:
+        raise ValueError("%s has %d elements, the plan needs nx*ny = %d" % (name, t.numel(), p.nx * p.ny))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def solve(p, f, u, stream=None, raise_on_error=False):
+    """Solves A u = f in place (u: guess in, solution out).  Returns the result dict;
+    status 'stagnated' and 'not_converged' are results, not exceptions, unless
+    raise_on_error is set.  Argument and runtime errors raise CJError."""
+    r = Result()
+    code = lib().cj_solve(p.handle, _grid_ptr(f, p, "f"), _grid_ptr(u, p, "u"), _stream(stream), ctypes.byref(r))
+    if code in (CJ_ERR_ARG, CJ_ERR_NOMEM, CJ_ERR_HIP, CJ_ERR_DEVICE) or (raise_on_error and code != CJ_OK):
+        raise CJError(code, "cj_solve", last_error())
+    return r.as_dict()
+
+
+def sweeps(p, f, u, n, stream=None):
+    """Applies the first n sweeps of the plan's schedule to u in place."""
+    _check(lib().cj_sweeps(p.handle, _grid_ptr(f, p, "f"), _grid_ptr(u, p, "u"), int(n), _stream(stream)),
+           "cj_sweeps")
+
+
+def residual(p, f, u, stream=None):
+    """||f - A u|| / ||f||."""
+    out = ctypes.c_double()
+    _check(lib().cj_residual(p.handle, _grid_ptr(f, p, "f"), _grid_ptr(u, p, "u"), _stream(stream),
+                             ctypes.byref(out)), "cj_residual")
+    return out.value
+
+
+def apply(p, u, au, stream=None):
+    """au = A u."""
+    _check(lib().cj_apply(p.handle, _grid_ptr(u, p, "u"), _grid_ptr(au, p, "au"), _stream(stream)), "cj_apply")

@@ -1,0 +1,90 @@
+// Internal declarations shared by the host runtime and the kernel launchers of
+// libcj.so.  Not part of the public ABI (see include/cj.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <string>
+#include <vector>
+
+namespace cj {
+
+// ---------------------------------------------------------------- plan (host)
+
+struct Schedule {
+    int stencil = 9;
+    int nx = 0, ny = 0;
+    double tol = 0.0, h = 0.0;
+    double kmin = 0.0, kmax = 0.0, beta = 0.0, rho = 0.0;
+    int M = 0, cycles_pred = 0;
+    std::vector<double> w;   // M weights in applied order
+};
+
+// Fills s from (stencil, nx, ny, tol, h, M_request); returns false with a message on bad input.
+bool make_schedule(int stencil, int nx, int ny, double tol, double h, int M_request,
+                   Schedule* s, std::string* err);
+
+// ---------------------------------------------------------------- device layout
+
+// Padded, pitched storage of a grid function: node (x, y) for
+// -1 <= x <= nx + 2, -1 <= y <= ny + 2 lives at (y + 1) * pitch + (x + kXOff).
+// kXOff puts the first interior column x = 1 on a 128-byte boundary.  The ring
+// x in {0, nx+1}, y in {0, ny+1} holds the Dirichlet zeros; the outer ring
+// x in {-1, nx+2}, y in {-1, ny+2} holds the odd reflection of the interior
+// (read by the 17-point stencil only).
+constexpr int kXOff = 15;
+
+struct Layout {
+    int nx = 0, ny = 0;
+    int pitch = 0;          // doubles per stored row
+    size_t elems = 0;       // doubles per padded array
+};
+
+Layout make_layout(int nx, int ny);
+
+// Launch geometry of the tile kernels (sweeps, residual, stage-in).
+struct Tiles {
+    int width = 256;        // columns per workgroup = threads per workgroup (multiple of 64)
+    int rows = 64;          // rows per workgroup
+    int tiles_x = 0, tiles_y = 0;
+    int count() const { return tiles_x * tiles_y; }
+};
+
+Tiles make_tiles(int nx, int ny, int rows_request);
+
+// ---------------------------------------------------------------- launchers
+// Every launcher enqueues on `stream` and returns the launch status.
+
+// Interior of A and B <- u (user layout), interior of G <- scale * f; per-tile
+// partial sums of G^2 into part[0 .. tiles.count()).
+hipError_t launch_stage_in(const Layout& L, const Tiles& T, const double* f, const double* u,
+                           double scale, double* A, double* B, double* G, double* part,
+                           hipStream_t stream);
+
+// Ring of A, B (reflection of u) and G (zeros).
+hipError_t launch_ring(const Layout& L, const double* u, double* A, double* B, double* G,
+                       hipStream_t stream);
+
+// u (user layout) <- interior of A.
+hipError_t launch_stage_out(const Layout& L, const double* A, double* u, hipStream_t stream);
+
+// One weighted sweep uout <- uin + w[widx] * r(uin), r = g - D^{-1} A uin in
+// normalised form.  If part != nullptr, per-tile partial sums of r^2 of uin go
+// to part[0 .. tiles.count()).
+hipError_t launch_sweep(int stencil, const Layout& L, const Tiles& T, const double* uin,
+                        double* uout, const double* g, const double* w, int widx,
+                        double* part, hipStream_t stream);
+
+// Per-tile partial sums of r^2 of u (read-only).
+hipError_t launch_residual(int stencil, const Layout& L, const Tiles& T, const double* u,
+                           const double* g, double* part, hipStream_t stream);
+
+// out[0] <- sum of part[0 .. n) in a fixed order (one workgroup).
+hipError_t launch_reduce(const double* part, int n, double* out, hipStream_t stream);
+
+// au (user layout) <- dscale * (u - sum c_hat u_nbr) = A u, with dscale = D.
+hipError_t launch_apply(int stencil, const Layout& L, const double* A, double dscale,
+                        double* au, hipStream_t stream);
+
+}  // namespace cj

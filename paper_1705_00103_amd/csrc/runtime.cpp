@@ -1,0 +1,367 @@
+// Host runtime and C ABI of libcj.so (declared in include/cj.h).
+//
+// A plan holds the schedule (host, FP64) and, after the first device call, a
+// device workspace: two padded iterates A and B (ping-pong), the padded
+// scaled right-hand side G = D^{-1} f, the weights, the per-tile reduction
+// partials and a pinned 8-byte host slot for the cycle-end residual.
+//
+// Solve loop: the residual of the iterate reached at a cycle end is produced
+// by the first sweep of the next cycle (the sweep forms r anyway), so the
+// norm costs no extra pass over HBM.  The host waits for that 8-byte value
+// once per cycle and decides; if it stops, the sweep's input (still intact in
+// the other buffer) is the answer.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <initializer_list>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/cj.h"
+#include "cj_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+cj_status fail(cj_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+#define CJ_HIP(call)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(CJ_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+// Stencil facts used by the runtime: |c_centre| / s, where A = -(1/(s h^2)) sum c u.
+double centre_over_s(int stencil) {
+    switch (stencil) {
+    case 5: return 4.0;            // (1/h^2)[..., -4]
+    case 9: return 20.0 / 6.0;     // (1/(6h^2))[..., -20]
+    case 17: return 300.0 / 72.0;  // (1/(72h^2))[..., -300]
+    default: return NAN;
+    }
+}
+
+}  // namespace
+
+struct cj_plan_s {
+    cj::Schedule s;
+    cj_options opt;
+    int max_cycles = 0;
+    cj::Layout L;
+    cj::Tiles T;
+    double D = 0.0;       // diagonal of A: |c_centre| / (s h^2)
+    // device state
+    int device = -1;
+    double* A = nullptr;
+    double* B = nullptr;
+    double* G = nullptr;
+    double* W = nullptr;
+    double* part = nullptr;
+    double* scalar = nullptr;
+    double* host_slot = nullptr;   // pinned
+    hipEvent_t ev[2] = {nullptr, nullptr};   // bracket the plain sweeps of a cycle
+    size_t workspace_bytes() const {
+        return 3 * L.elems * sizeof(double) + (size_t)s.M * sizeof(double) +
+               ((size_t)T.count() + 64) * sizeof(double);
+    }
+};
+
+namespace {
+
+void release(cj_plan_s* p) {
+    if (p->device >= 0) {
+        int cur = -1;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(p->device);
+        for (double* d : {p->A, p->B, p->G, p->W, p->part, p->scalar})
+            if (d) (void)hipFree(d);
+        if (p->host_slot) (void)hipHostFree(p->host_slot);
+        for (hipEvent_t& e : p->ev)
+            if (e) (void)hipEventDestroy(e);
+        if (cur >= 0) (void)hipSetDevice(cur);
+    }
+    p->A = p->B = p->G = p->W = p->part = p->scalar = p->host_slot = nullptr;
+    p->ev[0] = p->ev[1] = nullptr;
+    p->device = -1;
+}
+
+// Binds the plan to the current device on first use and allocates the workspace.
+cj_status ensure_device(cj_plan_s* p, hipStream_t stream) {
+    int dev = -1;
+    CJ_HIP(hipGetDevice(&dev));
+    if (p->device >= 0) {
+        if (dev != p->device)
+            return fail(CJ_ERR_DEVICE, "plan was first used on device " + std::to_string(p->device) +
+                                           ", current device is " + std::to_string(dev));
+        return CJ_OK;
+    }
+    p->device = dev;
+    const size_t bytes = p->L.elems * sizeof(double);
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMalloc((void**)&p->A, bytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->B, bytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->G, bytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->W, (size_t)p->s.M * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&p->part, (size_t)p->T.count() * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&p->scalar, 64 * sizeof(double));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&p->host_slot, 64 * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreate(&p->ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&p->ev[1]);
+    if (e != hipSuccess) {
+        release(p);
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? CJ_ERR_NOMEM : CJ_ERR_HIP,
+                    std::string("workspace allocation: ") + hipGetErrorString(e));
+    }
+    CJ_HIP(hipMemcpyAsync(p->W, p->s.w.data(), (size_t)p->s.M * sizeof(double), hipMemcpyHostToDevice, stream));
+    return CJ_OK;
+}
+
+cj_status check_ptr(const void* ptr, const char* name) {
+    if (ptr == nullptr) return fail(CJ_ERR_ARG, std::string(name) + " is NULL");
+    if (reinterpret_cast<uintptr_t>(ptr) % 8 != 0) return fail(CJ_ERR_ARG, std::string(name) + " is not 8-byte aligned");
+    return CJ_OK;
+}
+
+// Sum of the per-tile partials, copied to the host (waits on the stream).
+cj_status read_sum(cj_plan_s* p, int n, hipStream_t stream, double* out) {
+    CJ_HIP(cj::launch_reduce(p->part, n, p->scalar, stream));
+    CJ_HIP(hipMemcpyAsync(p->host_slot, p->scalar, sizeof(double), hipMemcpyDeviceToHost, stream));
+    CJ_HIP(hipStreamSynchronize(stream));
+    *out = p->host_slot[0];
+    return CJ_OK;
+}
+
+// Stage-in of f and u; returns sum of G^2.
+cj_status stage_in(cj_plan_s* p, const double* f, const double* u, hipStream_t stream, double* g2) {
+    const double scale = p->s.h * p->s.h / centre_over_s(p->s.stencil);   // D^{-1}
+    CJ_HIP(cj::launch_ring(p->L, u, p->A, p->B, p->G, stream));
+    CJ_HIP(cj::launch_stage_in(p->L, p->T, f, u, scale, p->A, p->B, p->G, p->part, stream));
+    return read_sum(p, p->T.count(), stream, g2);
+}
+
+// Enqueues sweeps [first, first + n) of the cyclic schedule, starting from *cur.
+cj_status enqueue_sweeps(cj_plan_s* p, long long first, long long n, double** cur, double** nxt,
+                         hipStream_t stream) {
+    for (long long k = 0; k < n; ++k) {
+        const int widx = (int)((first + k) % p->s.M);
+        CJ_HIP(cj::launch_sweep(p->s.stencil, p->L, p->T, *cur, *nxt, p->G, p->W, widx, nullptr, stream));
+        std::swap(*cur, *nxt);
+    }
+    return CJ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void cj_options_init(cj_options* opt) {
+    if (opt) std::memset(opt, 0, sizeof(*opt));
+}
+
+cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol, const cj_options* opt, cj_plan_t* out) {
+    if (out == nullptr) return fail(CJ_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (bc != CJ_BC_DIRICHLET0) return fail(CJ_ERR_ARG, "only homogeneous Dirichlet data (bc = 0) is supported");
+    cj_options o;
+    cj_options_init(&o);
+    if (opt) o = *opt;
+    for (int r : o.reserved)
+        if (r != 0) return fail(CJ_ERR_ARG, "reserved option fields must be zero");
+    if (o.max_cycles < 0 || o.sweeps_per_launch < 0 || o.tile_rows < 0)
+        return fail(CJ_ERR_ARG, "negative option");
+    cj_plan_s* p = new (std::nothrow) cj_plan_s();
+    if (!p) return fail(CJ_ERR_NOMEM, "host allocation");
+    std::string err;
+    if (!cj::make_schedule(stencil, nx, ny, tol, o.h, o.M, &p->s, &err)) {
+        delete p;
+        return fail(CJ_ERR_ARG, err);
+    }
+    p->opt = o;
+    p->max_cycles = o.max_cycles > 0 ? o.max_cycles : p->s.cycles_pred + 4;
+    p->L = cj::make_layout(nx, ny);
+    p->T = cj::make_tiles(nx, ny, o.tile_rows);
+    p->D = centre_over_s(stencil) / (p->s.h * p->s.h);
+    *out = p;
+    return CJ_OK;
+}
+
+cj_status cj_plan(int nx, int ny, int stencil, int bc, double tol, cj_plan_t* out) {
+    return cj_plan_ex(nx, ny, stencil, bc, tol, nullptr, out);
+}
+
+cj_status cj_plan_info(cj_plan_t p, double* kmin, double* kmax, int* M, int* cycles_pred,
+                       const double** weights_host, size_t* workspace_bytes) {
+    if (!p) return fail(CJ_ERR_ARG, "plan is NULL");
+    if (kmin) *kmin = p->s.kmin;
+    if (kmax) *kmax = p->s.kmax;
+    if (M) *M = p->s.M;
+    if (cycles_pred) *cycles_pred = p->s.cycles_pred;
+    if (weights_host) *weights_host = p->s.w.data();
+    if (workspace_bytes) *workspace_bytes = p->workspace_bytes();
+    return CJ_OK;
+}
+
+cj_status cj_solve(cj_plan_t p, const double* f, double* u, void* stream_, cj_result* res) {
+    const auto t0 = std::chrono::steady_clock::now();
+    cj_result r{};
+    auto finish = [&](cj_status s) {
+        r.status = s;
+        r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (res) *res = r;
+        return s;
+    };
+    if (!p) return finish(fail(CJ_ERR_ARG, "plan is NULL"));
+    cj_status st;
+    if ((st = check_ptr(f, "f")) != CJ_OK || (st = check_ptr(u, "u")) != CJ_OK) return finish(st);
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    if ((st = ensure_device(p, stream)) != CJ_OK) return finish(st);
+
+    double g2 = 0.0;
+    if ((st = stage_in(p, f, u, stream, &g2)) != CJ_OK) return finish(st);
+    if (!std::isfinite(g2)) return finish(fail(CJ_ERR_NONFINITE, "f has a NaN or Inf"));
+    if (g2 == 0.0) {
+        // f = 0: the solution is u = 0
+        hipError_t e = hipMemsetAsync(u, 0, (size_t)p->s.nx * (size_t)p->s.ny * sizeof(double), stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return finish(fail(CJ_ERR_HIP, hipGetErrorString(e)));
+        return finish(CJ_OK);
+    }
+    const double gnorm = std::sqrt(g2);
+    double* cur = p->A;
+    double* nxt = p->B;
+    const long long M = p->s.M;
+    double prev = 0.0;
+    cj_status outcome = CJ_OK;
+    int c = 0;
+    bool timed = false;   // events ev[0], ev[1] bracket the previous cycle's plain sweeps
+    for (;;) {
+        // first sweep of the next cycle, fused with the residual of its input
+        hipError_t e = cj::launch_sweep(p->s.stencil, p->L, p->T, cur, nxt, p->G, p->W, 0, p->part, stream);
+        if (e != hipSuccess) return finish(fail(CJ_ERR_HIP, hipGetErrorString(e)));
+        double r2 = 0.0;
+        if ((st = read_sum(p, p->T.count(), stream, &r2)) != CJ_OK) return finish(st);
+        if (timed) {
+            float ms = 0.0f;
+            CJ_HIP(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
+            r.sweep_seconds += 1e-3 * (double)ms;
+            r.sweep_launches += M - 1;
+            timed = false;
+        }
+        const double rr = std::sqrt(r2) / gnorm;
+        r.rel_residual = rr;
+        if (!std::isfinite(rr)) {
+            outcome = fail(CJ_ERR_NONFINITE, "residual is not finite (u has a NaN or Inf)");
+            break;
+        }
+        if (rr <= p->s.tol) {
+            outcome = CJ_OK;
+            break;
+        }
+        if (c >= 1 && c >= p->s.cycles_pred && rr > 0.5 * prev) {
+            outcome = CJ_STAGNATED;
+            r.floor_estimate = rr < prev ? rr : prev;
+            g_last_error = "residual stagnated above tol (FP64 floor)";
+            break;
+        }
+        if (c >= p->max_cycles) {
+            outcome = fail(CJ_ERR_NOT_CONVERGED, "max_cycles reached");
+            break;
+        }
+        prev = rr;
+        std::swap(cur, nxt);
+        if (M > 1) {
+            CJ_HIP(hipEventRecord(p->ev[0], stream));
+            if ((st = enqueue_sweeps(p, 1, M - 1, &cur, &nxt, stream)) != CJ_OK) return finish(st);
+            CJ_HIP(hipEventRecord(p->ev[1], stream));
+            timed = true;
+        }
+        ++c;
+    }
+    r.cycles = c;
+    r.sweeps = (long long)c * M;
+    hipError_t e = cj::launch_stage_out(p->L, cur, u, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return finish(fail(CJ_ERR_HIP, hipGetErrorString(e)));
+    return finish(outcome);
+}
+
+cj_status cj_sweeps(cj_plan_t p, const double* f, double* u, long long n_sweeps, void* stream_) {
+    if (!p) return fail(CJ_ERR_ARG, "plan is NULL");
+    if (n_sweeps < 0) return fail(CJ_ERR_ARG, "n_sweeps < 0");
+    cj_status st;
+    if ((st = check_ptr(f, "f")) != CJ_OK || (st = check_ptr(u, "u")) != CJ_OK) return st;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    if ((st = ensure_device(p, stream)) != CJ_OK) return st;
+    double g2 = 0.0;
+    if ((st = stage_in(p, f, u, stream, &g2)) != CJ_OK) return st;
+    double* cur = p->A;
+    double* nxt = p->B;
+    if ((st = enqueue_sweeps(p, 0, n_sweeps, &cur, &nxt, stream)) != CJ_OK) return st;
+    CJ_HIP(cj::launch_stage_out(p->L, cur, u, stream));
+    CJ_HIP(hipStreamSynchronize(stream));
+    return CJ_OK;
+}
+
+cj_status cj_residual(cj_plan_t p, const double* f, const double* u, void* stream_, double* rel_residual) {
+    if (!p) return fail(CJ_ERR_ARG, "plan is NULL");
+    if (!rel_residual) return fail(CJ_ERR_ARG, "rel_residual is NULL");
+    cj_status st;
+    if ((st = check_ptr(f, "f")) != CJ_OK || (st = check_ptr(u, "u")) != CJ_OK) return st;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    if ((st = ensure_device(p, stream)) != CJ_OK) return st;
+    double g2 = 0.0, r2 = 0.0;
+    if ((st = stage_in(p, f, u, stream, &g2)) != CJ_OK) return st;
+    CJ_HIP(cj::launch_residual(p->s.stencil, p->L, p->T, p->A, p->G, p->part, stream));
+    if ((st = read_sum(p, p->T.count(), stream, &r2)) != CJ_OK) return st;
+    *rel_residual = g2 == 0.0 ? 0.0 : std::sqrt(r2) / std::sqrt(g2);
+    if (!std::isfinite(*rel_residual)) return fail(CJ_ERR_NONFINITE, "f or u has a NaN or Inf");
+    return CJ_OK;
+}
+
+cj_status cj_apply(cj_plan_t p, const double* u, double* au, void* stream_) {
+    if (!p) return fail(CJ_ERR_ARG, "plan is NULL");
+    cj_status st;
+    if ((st = check_ptr(u, "u")) != CJ_OK || (st = check_ptr(au, "au")) != CJ_OK) return st;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    if ((st = ensure_device(p, stream)) != CJ_OK) return st;
+    double g2 = 0.0;
+    // stage u in (f is not needed: stage it from u too, G is unused here)
+    if ((st = stage_in(p, u, u, stream, &g2)) != CJ_OK) return st;
+    CJ_HIP(cj::launch_apply(p->s.stencil, p->L, p->A, p->D, au, stream));
+    CJ_HIP(hipStreamSynchronize(stream));
+    return CJ_OK;
+}
+
+void cj_plan_destroy(cj_plan_t p) {
+    if (!p) return;
+    release(p);
+    delete p;
+}
+
+const char* cj_status_string(int s) {
+    switch (s) {
+    case CJ_OK: return "CJ_OK";
+    case CJ_STAGNATED: return "CJ_STAGNATED";
+    case CJ_ERR_ARG: return "CJ_ERR_ARG";
+    case CJ_ERR_NOMEM: return "CJ_ERR_NOMEM";
+    case CJ_ERR_HIP: return "CJ_ERR_HIP";
+    case CJ_ERR_NOT_CONVERGED: return "CJ_ERR_NOT_CONVERGED";
+    case CJ_ERR_NONFINITE: return "CJ_ERR_NONFINITE";
+    case CJ_ERR_DEVICE: return "CJ_ERR_DEVICE";
+    default: return "CJ_UNKNOWN_STATUS";
+    }
+}
+
+const char* cj_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,220 @@
+"""GPU parity: libcj.so (through its C ABI) against the CPU oracle.
+
+Bar (FP64 path): relative L2 difference <= 1e-12 on the same inputs and the same
+weight schedule; statuses and cycle counts identical.  Inputs come from
+paper_1705_00103_amd.inputs; expected values from oracle/ only.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cjm, dense
+from paper_1705_00103_amd import cj, inputs
+
+pytestmark = pytest.mark.gpu
+
+REL_L2 = 1e-12       # FP64 parity bar
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_c1_manufactured_full_solve(torch_cuda):
+    """128 x 128 interior, 9-point, f = -Delta(sin pi x sin pi y), tol 1e-10."""
+    torch = torch_cuda
+    n, st, tol = 128, 9, 1e-10
+    _say("case: C1 128x128 9-point")
+    f = inputs.sinsin_rhs(n, n)
+    ref = cjm.solve(f, n, n, st, tol)
+    p = cj.plan(n, n, st, tol)
+    u = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+    r = cj.solve(p, _dev(torch, f), u)
+    assert r["status"] == "ok" == ref["status"]
+    assert r["cycles"] == ref["cycles"] == 8
+    # Near convergence r = g - D^{-1}A u cancels terms of size |u| ~ |g| / kmin, so the
+    # two residual evaluations differ by rounding noise ~ eps * kmax / kmin.
+    noise = 50 * np.finfo(float).eps * p.kmax / p.kmin
+    assert abs(r["rel_residual"] - ref["relres"]) <= 1e-6 * ref["relres"] + noise
+    assert _rel(_host(u), ref["u"]) <= REL_L2
+
+
+SHAPES = [(1, 1), (2, 3), (1, 70), (70, 1), (17, 5), (63, 47), (130, 64), (257, 33), (300, 70)]
+
+
+@pytest.mark.parametrize("st", [5, 9, 17])
+@pytest.mark.parametrize("nx,ny", SHAPES)
+def test_full_solve_parity(torch_cuda, st, nx, ny):
+    """Full solves on shapes that span several tiles, ragged tails and degenerate strips."""
+    torch = torch_cuda
+    tol = 1e-10
+    _say("case: solve", st, nx, ny)
+    f = inputs.gaussian_bumps_rhs(nx, ny, seed=1705 + nx * 7 + ny)
+    ref = cjm.solve(f, nx, ny, st, tol)
+    p = cj.plan(nx, ny, st, tol)
+    u = torch.zeros(ny, nx, dtype=torch.float64, device="cuda")
+    r = cj.solve(p, _dev(torch, f), u)
+    assert r["status"] == ref["status"]
+    assert r["cycles"] == ref["cycles"]
+    assert _rel(_host(u), ref["u"]) <= REL_L2
+
+
+@pytest.mark.parametrize("st", [5, 9, 17])
+def test_sweep_prefix_from_rough_guess(torch_cuda, st):
+    """A fixed prefix of sweeps (crossing a cycle boundary) from a random guess,
+    compared element by element."""
+    torch = torch_cuda
+    nx, ny = 301, 157
+    f = inputs.gaussian_bumps_rhs(nx, ny, seed=5)
+    u0 = inputs.random_field(nx, ny, seed=6)
+    p = cj.plan(nx, ny, st, 1e-6, M=16)
+    n = 37
+    ref = cjm.run_sweeps(f, nx, ny, st, 1e-6, n, M=16, u0=u0)
+    u = _dev(torch, u0)
+    cj.sweeps(p, _dev(torch, f), u, n)
+    got = _host(u)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_zero_sweeps_round_trip_is_exact(torch_cuda):
+    torch = torch_cuda
+    for st in (5, 9, 17):
+        nx, ny = 259, 67
+        u0 = inputs.random_field(nx, ny, seed=st)
+        p = cj.plan(nx, ny, st, 1e-8)
+        u = _dev(torch, u0)
+        cj.sweeps(p, _dev(torch, inputs.random_field(nx, ny, 1)), u, 0)
+        assert np.array_equal(_host(u), u0)
+
+
+@pytest.mark.parametrize("st", [5, 9, 17])
+def test_residual_and_apply(torch_cuda, st):
+    torch = torch_cuda
+    nx, ny = 190, 77
+    f = inputs.gaussian_bumps_rhs(nx, ny, seed=9)
+    u0 = inputs.random_field(nx, ny, seed=10, scale=1e-3)
+    p = cj.plan(nx, ny, st, 1e-8)
+    fd, ud = _dev(torch, f), _dev(torch, u0)
+    rr = cj.residual(p, fd, ud)
+    rr2 = cj.residual(p, fd, ud)
+    assert rr == rr2                         # deterministic reduction
+    ref = cjm.relative_residual(st, f, u0, nx, ny)
+    assert abs(rr - ref) <= 1e-12 * ref
+    au = torch.empty_like(ud)
+    cj.apply(p, ud, au)
+    ref_au = cjm.apply(st, u0, nx, ny)
+    h = cjm.spacing(nx, ny)
+    scale = np.abs(u0).max() * 8.0 / (h * h)   # magnitude of the terms summed
+    assert np.abs(_host(au) - ref_au).max() <= 1e-14 * scale
+
+
+def test_status_paths(torch_cuda):
+    torch = torch_cuda
+    n = 40
+    f = inputs.random_field(n, n, 5)
+    p = cj.plan(n, n, 9, 1e-8)
+    g = f.copy()
+    g[3, 4] = np.nan
+    u = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+    assert cj.solve(p, _dev(torch, g), u)["status"] == "nonfinite"
+    u = _dev(torch, inputs.random_field(n, n, 1))
+    r = cj.solve(p, torch.zeros(n, n, dtype=torch.float64, device="cuda"), u)
+    assert r["status"] == "ok" and not _host(u).any()
+    p1 = cj.plan(n, n, 9, 1e-12, max_cycles=1)
+    u = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+    r = cj.solve(p1, _dev(torch, f), u)
+    ref = cjm.solve(f, n, n, 9, 1e-12, max_cycles=1)
+    assert r["status"] == "not_converged" == ref["status"] and r["cycles"] == 1
+    assert _rel(_host(u), ref["u"]) <= REL_L2
+    p2 = cj.plan(n, n, 9, 1e-17)
+    u = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+    r = cj.solve(p2, _dev(torch, f), u)
+    assert r["status"] == "stagnated"
+    assert r["cycles"] >= p2.cycles_pred and r["floor_estimate"] > 0
+    # a converged guess costs no cycle
+    ref = cjm.solve(f, n, n, 9, 1e-12)["u"]
+    u = _dev(torch, ref)
+    r = cj.solve(p, _dev(torch, f), u)
+    assert r["status"] == "ok" and r["cycles"] == 0
+    assert np.array_equal(_host(u), ref)
+
+
+def _sample_points(nx, ny, rng, k=24):
+    pts = [(1, 1), (nx, 1), (1, ny), (nx, ny), (2, ny // 2), (nx // 2, 2), (nx - 1, ny - 1),
+           (256, 64), (257, 65), (256 * 3, 64 * 5 + 1)]
+    pts += [(int(rng.integers(1, nx + 1)), int(rng.integers(1, ny + 1))) for _ in range(k)]
+    return [(min(i, nx), min(j, ny)) for (i, j) in pts]
+
+
+@pytest.mark.parametrize("st", [9, 17, 5])
+@pytest.mark.parametrize("n", [4096, 8192])
+def test_full_size_sampled_sweeps(torch_cuda, st, n):
+    """At the benchmark sizes and launch configuration: a prefix of sweeps from a
+    rough guess, sampled at edges, corners, tile seams and random nodes; each
+    sample is computed by the oracle on its own domain of dependence."""
+    torch = torch_cuda
+    _say("case: full-size sampled", st, n)
+    f = inputs.gaussian_bumps_rhs(n, n, seed=1705 + st)
+    u0 = inputs.random_field(n, n, seed=17, scale=1e-3)
+    p = cj.plan(n, n, st, 1e-10)
+    nsw = 6
+    u = _dev(torch, u0)
+    cj.sweeps(p, _dev(torch, f), u, nsw)
+    got = _host(u)
+    pts = _sample_points(n, n, np.random.default_rng(n + st))
+    ref = cjm.sampled_sweeps(f, u0, n, n, st, 1e-10, nsw, pts)
+    vals = np.array([got[j - 1, i - 1] for (i, j) in pts])
+    scale = np.abs(ref).max()
+    assert np.abs(vals - ref).max() <= 1e-12 * scale
+
+
+def test_full_size_solve_against_exact_solution(torch_cuda):
+    """4096 x 4096, 9-point, bumps: the full GPU solve against the exact discrete
+    solution (sine transform) and its residual recomputed by the oracle."""
+    torch = torch_cuda
+    n, st = 4096, 9
+    _say("case: 4096 full solve vs DST")
+    f = inputs.gaussian_bumps_rhs(n, n, seed=1705 + st)
+    p = cj.plan(n, n, st, 1e-10)
+    u = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+    r = cj.solve(p, _dev(torch, f), u)
+    assert r["status"] in ("ok", "stagnated")
+    got = _host(u)
+    rr = cjm.relative_residual(st, f, got, n, n)
+    taps, s = cjm.taps(st)
+    h = cjm.spacing(n, n)
+    exact = dense.dst_solve(taps, s, f, n, n, h)
+    err = _rel(got, exact)
+    _say("gpu relres %.3e  oracle relres %.3e  rel err vs DST %.3e  status %s cycles %d"
+         % (r["rel_residual"], rr, err, r["status"], r["cycles"]))
+    # Two FP64 evaluations of r = g - D^{-1}A u differ by rounding noise of order
+    # eps * ||u|| / ||g|| (terms of size |u| cancel down to |r|).
+    D = -dense.centre(taps) / (s * h * h)
+    noise = 8 * np.finfo(float).eps * np.linalg.norm(got) * D / np.linalg.norm(f)
+    assert abs(rr - r["rel_residual"]) <= 1e-3 * rr + noise
+    assert rr <= 5e-10          # FP64 floor at this size: the stored iterate cannot do better
+    assert err <= 1e-8
