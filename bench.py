@@ -8,10 +8,15 @@ sweeps with the fused cycle-end residual test, stage-out) of the workload
 with f already resident in HBM.  Prints one JSON line.
 
 value      = grid-point updates / s over the timed steps (updates = nx*ny*cycles*M)
-roofline   = the plain sweep kernel (the dominant one): algorithmic bytes per
-             launch (24 B per grid-point update: read u, read g, write u', FP64)
-             divided by its average launch duration, timed inside the library
-             with HIP events on the solve's stream, against 8 TB/s HBM.
+roofline   = the dominant kernel, the temporally blocked sweep (K sweeps per
+             launch): algorithmic bytes per launch = 24 B per grid-point update
+             (read u, read g, write u', FP64) x K updates x nx*ny points,
+             divided by its average launch duration (timed inside the library
+             with HIP events on the solve's stream), against 8 TB/s HBM.  With
+             K > 1 a launch touches HBM once for K updates, so frac can exceed 1;
+             `traffic` (rocprofv3 counters) gives the bytes actually moved.
+single_sweep_reference = the one-sweep-per-launch kernel on the same grid,
+             timed with HIP events on the solve's stream (24 B per update).
 cpu_baseline = the CPU oracle's sweep loop on the same workload, for a bounded
              number of sweeps (about --cpu-seconds of host time).
 """
@@ -32,7 +37,7 @@ METRIC = "grid-point updates/s + time-to-tol (1e-10 rel resid); p50/p99 solve la
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = 24.0   # FP64: u and g read, u' written
 KERNEL_SRC = os.path.join(ROOT, "paper_1705_00103_amd", "csrc", "kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep9_f64_8192_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweepk9_f64_8192_traffic.md")
 
 
 def kernel_hash():
@@ -54,6 +59,48 @@ def measured_traffic(n, stencil):
     if int(w.group(1)) != n or int(w.group(2)) != stencil:
         return None
     return float(t.group(1))
+
+
+def single_sweep_reference(cj, fd, n, st, tol, launches=48):
+    """Average duration of the one-sweep kernel, timed with events on the stream the
+    library launches on (torch's current stream is passed to it)."""
+    import torch
+    p1 = cj.plan(n, n, st, tol, sweeps_per_launch=1)
+    u = torch.zeros_like(fd)
+    cj.sweeps(p1, fd, u, 2)
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    cj.sweeps(p1, fd, u, 0)
+    e1.record()
+    cj.sweeps(p1, fd, u, launches)
+    e2.record()
+    torch.cuda.synchronize()
+    dt = (e1.elapsed_time(e2) - e0.elapsed_time(e1)) * 1e-3 / launches
+    p1.destroy()
+    achieved = BYTES_PER_UPDATE * n * n / dt / 1e9
+    return {"kernel": "sweep_kernel<%d, write, no-norm> (1 sweep per launch)" % st, "avg_launch_us": round(dt * 1e6, 2),
+            "achieved": round(achieved, 1), "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
+
+
+def traffic_probe(n, st, tol, launches=4):
+    """Short run for rocprofv3 counter passes: a plain copy of known size (for the
+    counter calibration) and a few launches of each sweep kernel."""
+    import torch
+    from paper_1705_00103_amd import cj, inputs
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")     # 1 GiB
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    fd = torch.from_numpy(inputs.gaussian_bumps_rhs(n, n, seed=1705 + st)).to("cuda")
+    u = torch.zeros_like(fd)
+    pk = cj.plan(n, n, st, tol)
+    cj.sweeps(pk, fd, u, launches * pk.sweeps_per_launch)
+    p1 = cj.plan(n, n, st, tol, sweeps_per_launch=1)
+    cj.sweeps(p1, fd, u, launches)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "traffic", "copy_bytes_each": 2 * a.numel() * 8, "copies": 3, "n": n,
+                      "stencil": st, "K": pk.sweeps_per_launch, "blocked_launches": launches,
+                      "single_launches": launches}), flush=True)
 
 
 def cpu_baseline(f, n, stencil, tol, budget_s):
@@ -88,12 +135,14 @@ def main():
     ap.add_argument("--seed", type=int, default=None, help="RHS seed (default 1705 + stencil)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run only the short copy + sweep probe used for rocprofv3 counter passes")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
-              "(a single solve is one GPU's work; see DESIGN.md for how it would shard)" % args.gpus,
+              "(a single solve is one GPU's work)" % args.gpus,
               file=sys.stderr, flush=True)
         sys.exit(2)
 
@@ -103,6 +152,9 @@ def main():
     from paper_1705_00103_amd import cj, inputs
 
     n, st, tol = args.n, args.stencil, args.tol
+    if args.traffic_probe:
+        traffic_probe(n, st, tol)
+        return
     seed = 1705 + st if args.seed is None else args.seed
     f = inputs.gaussian_bumps_rhs(n, n, seed=seed)
     fd = torch.from_numpy(f).to("cuda")
@@ -132,16 +184,21 @@ def main():
 
     sweep_s = sum(r["sweep_seconds"] for r in res)
     launches = sum(r["sweep_launches"] for r in res)
+    K = p.sweeps_per_launch
     roofline = None
     if launches > 0:
         avg = sweep_s / launches
-        algo = BYTES_PER_UPDATE * n * n
+        algo = BYTES_PER_UPDATE * K * n * n
         achieved = algo / avg / 1e9
         traffic = measured_traffic(n, st)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                    "kernel": "sweep_kernel<%d, write, no-norm>" % st,
-                    "avg_launch_us": round(avg * 1e6, 2), "algorithmic_bytes_per_launch": algo}
+                    "kernel": "sweepk_kernel<%d, K=%d, no-norm>" % (st, K), "sweeps_per_launch": K,
+                    "avg_launch_us": round(avg * 1e6, 2), "algorithmic_bytes_per_launch": algo,
+                    "compulsory_hbm_bytes_per_launch": BYTES_PER_UPDATE * n * n}
+        if traffic:
+            roofline["traffic_gbs"] = round(traffic / avg / 1e9, 1)
+    single = single_sweep_reference(cj, fd, n, st, tol)
 
     lat_ms = sorted(x * 1e3 for x in lat)
     p50 = float(np.percentile(lat_ms, 50))
@@ -168,7 +225,8 @@ def main():
         "config": {
             "workload": "cjm-fp64-%dpt-%dx%d-bumps16-tol%g" % (st, n, n, tol),
             "nx": n, "ny": n, "stencil": st, "tol": tol, "rhs_seed": seed, "M": p.M,
-            "cycles_pred": p.cycles_pred, "parallelism": "single-gpu",
+            "cycles_pred": p.cycles_pred, "sweeps_per_launch": K, "tile_rows": p.tile_rows,
+            "parallelism": "single-gpu",
         },
         "time_to_tol_p50_ms": p50,
         "time_to_tol_p99_ms": p99,
@@ -178,6 +236,7 @@ def main():
         "rel_residual": last["rel_residual"],
         "effective_tol": last["rel_residual"] if last["status"] == "stagnated" else tol,
         "roofline": roofline,
+        "single_sweep_reference": single,
         "cpu_baseline": cpu,
     }
     if cpu is not None:

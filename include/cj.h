@@ -67,7 +67,10 @@ typedef struct {
                                   (predicted cycles x M), ties to the smaller; else a
                                   power of two, 1 <= M <= 2^24 */
     int    max_cycles;         /* 0 = predicted cycles + 4 */
-    int    sweeps_per_launch;  /* temporal-blocking depth k of the sweep kernels, 0 = auto */
+    int    sweeps_per_launch;  /* temporal-blocking depth K of the sweep kernel: sweeps fused
+                                  into one launch; 0 = automatic (8 for the 5- and 9-point
+                                  stencils, 3 for 17 points); 1, 2, 3, 4, 6, 8 (5/9-point)
+                                  or 1, 2, 3, 4 (17-point) */
     int    tile_rows;          /* rows per workgroup tile of the sweep kernel, 0 = auto */
     double h;                  /* mesh spacing; 0 = 1 / max(nx + 1, ny + 1) */
     int    reserved[8];        /* must be zero */
@@ -109,6 +112,11 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol,
  * the reduction buffers. */
 cj_status cj_plan_info(cj_plan_t p, double* kmin, double* kmax, int* M, int* cycles_pred,
                        const double** weights_host, size_t* workspace_bytes);
+
+/* Launch geometry of the plan's sweep kernel: sweeps fused per launch
+ * (temporal-blocking depth K), output rows per workgroup tile and
+ * workgroups per launch.  Any output pointer may be NULL. */
+cj_status cj_plan_launch_info(cj_plan_t p, int* sweeps_per_launch, int* tile_rows, int* workgroups);
 
 /* Solves A u = f.  u is read as the initial guess and overwritten with the
  * solution.  Cycles of M sweeps are run; the relative residual

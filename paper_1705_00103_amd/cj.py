@@ -32,7 +32,7 @@ STATUS_NAMES = {
 }
 
 # Function names declared in include/cj.h (checked against the header by the tests).
-EXPORTS = ("cj_options_init", "cj_plan", "cj_plan_ex", "cj_plan_info", "cj_solve", "cj_sweeps",
+EXPORTS = ("cj_options_init", "cj_plan", "cj_plan_ex", "cj_plan_info", "cj_plan_launch_info", "cj_solve", "cj_sweeps",
            "cj_residual", "cj_apply", "cj_plan_destroy", "cj_status_string", "cj_last_error")
 
 
@@ -83,6 +83,8 @@ def lib():
         L.cj_plan_ex.restype = c_int
         L.cj_plan_info.argtypes = [vp, dp, dp, ip, ip, ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_size_t)]
         L.cj_plan_info.restype = c_int
+        L.cj_plan_launch_info.argtypes = [vp, ip, ip, ip]
+        L.cj_plan_launch_info.restype = c_int
         L.cj_solve.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Result)]
         L.cj_solve.restype = c_int
         L.cj_sweeps.argtypes = [vp, vp, vp, ctypes.c_longlong, vp]
@@ -137,6 +139,10 @@ class Plan:
         self.kmin, self.kmax, self.M, self.cycles_pred = kmin.value, kmax.value, Mo.value, cp.value
         self.weights = [w[k] for k in range(self.M)]
         self.workspace_bytes = ws.value
+        k, rows, wg = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(L.cj_plan_launch_info(handle, ctypes.byref(k), ctypes.byref(rows), ctypes.byref(wg)),
+               "cj_plan_launch_info")
+        self.sweeps_per_launch, self.tile_rows, self.workgroups = k.value, rows.value, wg.value
 
     @property
     def handle(self):

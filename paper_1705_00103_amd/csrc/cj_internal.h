@@ -53,6 +53,10 @@ struct Tiles {
 
 Tiles make_tiles(int nx, int ny, int rows_request);
 
+// Geometry of the temporally blocked kernel: strips of 256 - 2KR output
+// columns (tiles_x strips) by tiles of `rows` output rows.
+Tiles make_tiles_k(int nx, int ny, int K, int R, int rows_request);
+
 // ---------------------------------------------------------------- launchers
 // Every launcher enqueues on `stream` and returns the launch status.
 
@@ -75,6 +79,13 @@ hipError_t launch_stage_out(const Layout& L, const double* A, double* u, hipStre
 hipError_t launch_sweep(int stencil, const Layout& L, const Tiles& T, const double* uin,
                         double* uout, const double* g, const double* w, int widx,
                         double* part, hipStream_t stream);
+
+// K sweeps in one launch (weights w[widx .. widx+K-1]), bit-identical to K
+// launch_sweep calls.  If part != nullptr, per-tile partial sums of r^2 of uin
+// go to part[0 .. tiles.count()).  T must come from make_tiles_k.
+bool sweepk_supported(int stencil, int K);
+hipError_t launch_sweepk(int stencil, int K, const Layout& L, const Tiles& T, const double* uin, double* uout,
+                         const double* g, const double* w, int widx, double* part, hipStream_t stream);
 
 // Per-tile partial sums of r^2 of u (read-only).
 hipError_t launch_residual(int stencil, const Layout& L, const Tiles& T, const double* u,

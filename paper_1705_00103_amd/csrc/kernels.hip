@@ -95,6 +95,29 @@ __device__ __forceinline__ double block_sum(double v) {
     return tot;
 }
 
+// Stores u'(x, y) with a streaming (non-temporal) store: the new iterate is not
+// read again before it has left the caches.  For the 17-point stencil the odd
+// reflections on the outer ring are kept up to date as well.
+template <int ST>
+__device__ __forceinline__ void store_update(double* __restrict__ uout, int pitch, int nx, int ny, int x, int y,
+                                             double un) {
+    __builtin_nontemporal_store(un, uout + at(pitch, x, y));
+    if (ST == 17) {
+        if (x == 1) uout[at(pitch, -1, y)] = -un;
+        if (x == nx) uout[at(pitch, nx + 2, y)] = -un;
+        if (y == 1) {
+            uout[at(pitch, x, -1)] = -un;
+            if (x == 1) uout[at(pitch, -1, -1)] = un;
+            if (x == nx) uout[at(pitch, nx + 2, -1)] = un;
+        }
+        if (y == ny) {
+            uout[at(pitch, x, ny + 2)] = -un;
+            if (x == 1) uout[at(pitch, -1, ny + 2)] = un;
+            if (x == nx) uout[at(pitch, nx + 2, ny + 2)] = un;
+        }
+    }
+}
+
 // ------------------------------------------------------------ sweep / residual
 // One lane per column x of a tile of width blockDim.x and `rows` rows.  The
 // lane keeps the window rows y-R .. y+R in registers and loads one new row
@@ -134,32 +157,230 @@ __global__ __launch_bounds__(256) void sweep_kernel(
         const double* p = uin + at(pitch, xl - R, y + R);
 #pragma unroll
         for (int c = 0; c < W; ++c) v[W - 1][c] = p[c];
-        const double gv = g[at(pitch, xl, y)];
+        const double gv = __builtin_nontemporal_load(g + at(pitch, xl, y));
         const double uc = v[R][R];
         const double res = (gv + neighbour_sum<ST>(v)) - uc;
         if (NORM) acc = fma(res, res, acc);
-        if (WRITE && active) {
-            const double un = fma(omega, res, uc);
-            uout[at(pitch, x, y)] = un;
-            if (ST == 17) {
-                // keep the outer ring the odd reflection of the new iterate
-                if (x == 1) uout[at(pitch, -1, y)] = -un;
-                if (x == nx) uout[at(pitch, nx + 2, y)] = -un;
-                if (y == 1) {
-                    uout[at(pitch, x, -1)] = -un;
-                    if (x == 1) uout[at(pitch, -1, -1)] = un;
-                    if (x == nx) uout[at(pitch, nx + 2, -1)] = un;
-                }
-                if (y == ny) {
-                    uout[at(pitch, x, ny + 2)] = -un;
-                    if (x == 1) uout[at(pitch, -1, ny + 2)] = un;
-                    if (x == nx) uout[at(pitch, nx + 2, ny + 2)] = un;
-                }
-            }
-        }
+        if (WRITE && active) store_update<ST>(uout, pitch, nx, ny, x, y, fma(omega, res, uc));
     }
     if (NORM) {
         if (!active) acc = 0.0;
+        const double tot = block_sum(acc);
+        if (threadIdx.x == 0) part[tile] = tot;
+    }
+}
+
+// ------------------------------------------------------------ temporal blocking
+// K consecutive weighted sweeps in one launch.  A workgroup of 256 lanes owns a
+// strip of 256 columns and marches up the rows of its tile; level s (the
+// iterate after s sweeps) trails level s-1 by R+1 rows, so that each level
+// only needs rows of the level below that were finished in an earlier step:
+// one barrier per row step suffices.  Level 0 comes from HBM (the row and its
+// x +- R neighbours), levels 1..K-1 are exchanged between lanes through LDS,
+// and every lane keeps a (2R+1) x (2R+1) register window per level, each row
+// tagged with the lane's value of g on that row (the g a level used for a row
+// is the g the next level needs on it).  Only level K is written back, so one
+// launch moves 24 bytes per grid point and performs K updates per point.
+// Outputs shrink by R columns per level on each side of the strip
+// (256 - 2KR output columns) and the tiles overlap in y by KR rows.
+// The row loop is unrolled by the window height W = 2R+1 so that the window
+// rotation is a compile-time renaming of registers.  Workgroups whose halo
+// reaches the domain boundary take a variant that closes the levels >= 1 with
+// the Dirichlet zeros and the odd reflections; interior workgroups skip it.
+// Every update evaluates exactly the expression of sweep_kernel on exactly the
+// same values, so K sweeps here give the same bits as K launches of it.
+
+template <int ST, int K>
+struct March {
+    static constexpr int R = Stencil<ST>::R;
+    static constexpr int W = 2 * R + 1;
+    static constexpr int WOUT = 256 - 2 * K * R;
+    double win[K][W][W];   // [level][physical row slot][column x-R .. x+R]
+    double gw[K][W];       // g of the lane's column on each window row
+    double own[K];         // the lane's value of the row a level produced in this step
+    double gused[K];       // the g it used
+    double pre[W];         // prefetched level-0 row
+    double pg;             // and its g
+    int lcol[W];           // level-0 load columns (clamped), with the layout offset
+    int xsrc[W];           // exchange source lanes for the x +- R neighbours
+    int xsgn[W];           // 1, 0 (Dirichlet column) or -1 (reflection), edge workgroups only
+};
+
+// One row step with compile-time phase J = t mod W.  Level 0 enters slot J at
+// the start of the step; level s >= 1 enters slot J at its end.
+template <int ST, int K, bool NORM, bool EDGE, int J>
+__device__ __forceinline__ void march_step(March<ST, K>& S, double (*xch)[March<ST, K>::W][256],
+                                           const double* __restrict__ uin, double* __restrict__ uout,
+                                           const double* __restrict__ g, const double (&om)[K], int t,
+                                           int ybase, int x, int xg, bool out_col, int Y0, int Y1, int nx,
+                                           int ny, int pitch, double& acc) {
+    constexpr int R = Stencil<ST>::R;
+    constexpr int W = 2 * R + 1;
+    const int tid = threadIdx.x;
+    const int yl = ybase + t;
+#pragma unroll
+    for (int c = 0; c < W; ++c) S.win[0][J][c] = S.pre[c];
+    S.gw[0][J] = S.pg;
+    {   // prefetch the next level-0 row and its g
+        const int yr = min(max(yl + 1, -1), ny + 2);
+        const double* rowp = uin + (size_t)(yr + 1) * (size_t)pitch;
+#pragma unroll
+        for (int c = 0; c < W; ++c) S.pre[c] = rowp[S.lcol[c]];
+        S.pg = __builtin_nontemporal_load(g + at(pitch, xg, yr));
+    }
+#pragma unroll
+    for (int s = 1; s <= K; ++s) {
+        const int Y = yl - (s - 1) - s * R;   // row produced by level s in this step
+        // logical window row r (0 = oldest) of level s-1 sits in physical slot
+        // (J + 1 + r) % W for level 0 (filled this step) and (J + r) % W above
+        double v[W][W];
+        double gv;
+#pragma unroll
+        for (int r = 0; r < W; ++r) {
+            const int ph = (s == 1) ? (J + 1 + r) % W : (J + r) % W;
+#pragma unroll
+            for (int c = 0; c < W; ++c) v[r][c] = S.win[s - 1][ph][c];
+            if (r == R) gv = S.gw[s - 1][ph];
+        }
+        if (EDGE && s > 1 && (Y - R < 1 || Y + R > ny)) {
+            // rows beyond the interior: Dirichlet zeros, second ring by odd reflection
+#pragma unroll
+            for (int r = 0; r < W; ++r) {
+                const int q = Y - R + r;
+                if (q == 0 || q == ny + 1) {
+#pragma unroll
+                    for (int c = 0; c < W; ++c) v[r][c] = 0.0;
+                } else if (R == 2 && q == -1 && r + 2 < W) {
+#pragma unroll
+                    for (int c = 0; c < W; ++c) v[r][c] = -v[r + 2][c];
+                } else if (R == 2 && q == ny + 2 && r >= 2) {
+#pragma unroll
+                    for (int c = 0; c < W; ++c) v[r][c] = -v[r - 2][c];
+                }
+            }
+        }
+        const double uc = v[R][R];
+        const double res = (gv + neighbour_sum<ST>(v)) - uc;
+        const double un = fma(om[s - 1], res, uc);
+        if (NORM && s == 1 && out_col && Y >= Y0 && Y < Y1) acc = fma(res, res, acc);
+        if (s < K) {
+            xch[s - 1][J][tid] = un;
+            S.own[s] = un;
+            S.gused[s] = gv;
+        } else if (out_col && Y >= Y0 && Y < Y1) {
+            store_update<ST>(uout, pitch, nx, ny, x, Y, un);
+        }
+    }
+    if (K > 1) {
+        __syncthreads();
+#pragma unroll
+        for (int s = 1; s < K; ++s) {
+#pragma unroll
+            for (int c = 0; c < W; ++c) {
+                double val;
+                if (c == R) {
+                    val = S.own[s];
+                } else {
+                    const double e = xch[s - 1][J][S.xsrc[c]];
+                    if (EDGE)
+                        val = S.xsgn[c] == 0 ? 0.0 : (S.xsgn[c] < 0 ? -e : e);
+                    else
+                        val = e;
+                }
+                S.win[s][J][c] = val;
+            }
+            S.gw[s][J] = S.gused[s];
+        }
+    }
+}
+
+template <int ST, int K, bool NORM, bool EDGE>
+__device__ __forceinline__ void march(March<ST, K>& S, double (*xch)[March<ST, K>::W][256],
+                                      const double* __restrict__ uin, double* __restrict__ uout,
+                                      const double* __restrict__ g, const double (&om)[K], int ybase, int steps,
+                                      int x, int xg, bool out_col, int Y0, int Y1, int nx, int ny, int pitch,
+                                      double& acc) {
+    constexpr int W = March<ST, K>::W;
+    for (int t = 0; t < steps; t += W) {
+        march_step<ST, K, NORM, EDGE, 0>(S, xch, uin, uout, g, om, t, ybase, x, xg, out_col, Y0, Y1, nx, ny,
+                                         pitch, acc);
+        march_step<ST, K, NORM, EDGE, 1>(S, xch, uin, uout, g, om, t + 1, ybase, x, xg, out_col, Y0, Y1, nx, ny,
+                                         pitch, acc);
+        march_step<ST, K, NORM, EDGE, 2>(S, xch, uin, uout, g, om, t + 2, ybase, x, xg, out_col, Y0, Y1, nx, ny,
+                                         pitch, acc);
+        if constexpr (W == 5) {
+            march_step<ST, K, NORM, EDGE, 3>(S, xch, uin, uout, g, om, t + 3, ybase, x, xg, out_col, Y0, Y1, nx,
+                                             ny, pitch, acc);
+            march_step<ST, K, NORM, EDGE, 4>(S, xch, uin, uout, g, om, t + 4, ybase, x, xg, out_col, Y0, Y1, nx,
+                                             ny, pitch, acc);
+        }
+    }
+}
+
+template <int ST, int K, bool NORM>
+__global__ __launch_bounds__(256) void sweepk_kernel(
+    const double* __restrict__ uin, double* __restrict__ uout, const double* __restrict__ g,
+    const double* __restrict__ w, int widx, int nx, int ny, int pitch, int strips_x, int rows,
+    double* __restrict__ part) {
+    using MS = March<ST, K>;
+    constexpr int R = MS::R;
+    constexpr int W = MS::W;
+    constexpr int WOUT = MS::WOUT;
+    __shared__ double xch[K > 1 ? K - 1 : 1][W][256];
+
+    const int tid = threadIdx.x;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int sx = tile % strips_x, sy = tile / strips_x;
+    const int X0 = sx * WOUT + 1;
+    const int x = X0 - K * R + tid;
+    const int Y0 = sy * rows + 1;
+    const int Y1 = min(Y0 + rows, ny + 1);
+    const bool out_col = tid >= K * R && tid < K * R + WOUT && x >= 1 && x <= nx;
+    const int xg = min(max(x, 1), nx);     // column for g (only interior columns matter)
+    // Does the halo of this workgroup reach beyond the interior?  (uniform)
+    const bool edge = (X0 - K * R < 1) || (X0 - K * R + 255 > nx) || (Y0 - K * R < 1) || (Y1 - 1 + K * R > ny);
+
+    MS S;
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+        S.lcol[c] = min(max(x - R + c, -1), nx + 2) + kXOff;
+        const int dx = c - R, col = x + dx;
+        int idx = tid + dx, sg = 1;
+        if (col == 0 || col == nx + 1) sg = 0;
+        else if (col == -1) { idx = tid + dx + 2; sg = -1; }
+        else if (col == nx + 2) { idx = tid + dx - 2; sg = -1; }
+        S.xsrc[c] = min(max(idx, 0), 255);
+        S.xsgn[c] = sg;
+    }
+    double om[K];
+#pragma unroll
+    for (int s = 0; s < K; ++s) om[s] = w[widx + s];
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+#pragma unroll
+        for (int r = 0; r < W; ++r) {
+            S.gw[s][r] = 0.0;
+#pragma unroll
+            for (int c = 0; c < W; ++c) S.win[s][r][c] = 0.0;
+        }
+    }
+    const int ybase = Y0 - K * R;   // level-0 row entering at step 0
+    {
+        const int yr = min(max(ybase, -1), ny + 2);
+        const double* rowp = uin + (size_t)(yr + 1) * (size_t)pitch;
+#pragma unroll
+        for (int c = 0; c < W; ++c) S.pre[c] = rowp[S.lcol[c]];
+        S.pg = __builtin_nontemporal_load(g + at(pitch, xg, yr));
+    }
+    double acc = 0.0;
+    const int steps = (Y1 - Y0) + 2 * K * R + K - 1;
+    if (edge)
+        march<ST, K, NORM, true>(S, xch, uin, uout, g, om, ybase, steps, x, xg, out_col, Y0, Y1, nx, ny, pitch,
+                                 acc);
+    else
+        march<ST, K, NORM, false>(S, xch, uin, uout, g, om, ybase, steps, x, xg, out_col, Y0, Y1, nx, ny, pitch,
+                                  acc);
+    if (NORM) {
         const double tot = block_sum(acc);
         if (threadIdx.x == 0) part[tile] = tot;
     }
@@ -316,6 +537,36 @@ hipError_t launch_sweep(int stencil, const Layout& L, const Tiles& T, const doub
     }
 }
 
+namespace {
+template <int ST, int K>
+hipError_t launch_k(const Layout& L, const Tiles& T, const double* uin, double* uout, const double* g,
+                    const double* w, int widx, double* part, hipStream_t s) {
+    if (part)
+        hipLaunchKernelGGL((sweepk_kernel<ST, K, true>), dim3(T.count()), dim3(256), 0, s, uin, uout, g, w, widx,
+                           L.nx, L.ny, L.pitch, T.tiles_x, T.rows, part);
+    else
+        hipLaunchKernelGGL((sweepk_kernel<ST, K, false>), dim3(T.count()), dim3(256), 0, s, uin, uout, g, w, widx,
+                           L.nx, L.ny, L.pitch, T.tiles_x, T.rows, part);
+    return hipGetLastError();
+}
+}  // namespace
+
+bool sweepk_supported(int stencil, int K) {
+    if (stencil == 17) return K == 2 || K == 3 || K == 4;
+    return K == 2 || K == 3 || K == 4 || K == 6 || K == 8;
+}
+
+hipError_t launch_sweepk(int stencil, int K, const Layout& L, const Tiles& T, const double* uin, double* uout,
+                         const double* g, const double* w, int widx, double* part, hipStream_t stream) {
+#define CJ_K_CASE(ST, KK) \
+    if (stencil == ST && K == KK) return launch_k<ST, KK>(L, T, uin, uout, g, w, widx, part, stream);
+    CJ_K_CASE(5, 2) CJ_K_CASE(5, 3) CJ_K_CASE(5, 4) CJ_K_CASE(5, 6) CJ_K_CASE(5, 8)
+    CJ_K_CASE(9, 2) CJ_K_CASE(9, 3) CJ_K_CASE(9, 4) CJ_K_CASE(9, 6) CJ_K_CASE(9, 8)
+    CJ_K_CASE(17, 2) CJ_K_CASE(17, 3) CJ_K_CASE(17, 4)
+#undef CJ_K_CASE
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_residual(int stencil, const Layout& L, const Tiles& T, const double* u, const double* g,
                            double* part, hipStream_t stream) {
     switch (stencil) {
@@ -358,11 +609,24 @@ Layout make_layout(int nx, int ny) {
     return L;
 }
 
+Tiles make_tiles_k(int nx, int ny, int K, int R, int rows_request) {
+    Tiles T;
+    T.width = 256 - 2 * K * R;               // output columns per strip
+    T.tiles_x = (nx + T.width - 1) / T.width;
+    int rows = rows_request > 0 ? rows_request : 128;
+    if (rows_request <= 0)
+        while (rows > 16 && (long long)T.tiles_x * ((ny + rows - 1) / rows) < 2048) rows /= 2;
+    if (rows > ny) rows = ny;
+    T.rows = rows;
+    T.tiles_y = (ny + rows - 1) / rows;
+    return T;
+}
+
 Tiles make_tiles(int nx, int ny, int rows_request) {
     Tiles T;
     T.width = nx >= 256 ? 256 : ((nx + 63) / 64) * 64;
     T.tiles_x = (nx + T.width - 1) / T.width;
-    int rows = rows_request > 0 ? rows_request : 64;
+    int rows = rows_request > 0 ? rows_request : 16;
     if (rows_request <= 0)
         while (rows > 4 && (long long)T.tiles_x * ((ny + rows - 1) / rows) < 2048) rows /= 2;
     if (rows > ny) rows = ny;

@@ -57,7 +57,9 @@ struct cj_plan_s {
     cj_options opt;
     int max_cycles = 0;
     cj::Layout L;
-    cj::Tiles T;
+    cj::Tiles T;          // single-sweep, stage-in and residual kernels
+    cj::Tiles TK;         // temporally blocked kernel (K > 1)
+    int K = 1;            // sweeps per launch
     double D = 0.0;       // diagonal of A: |c_centre| / (s h^2)
     // device state
     int device = -1;
@@ -71,8 +73,9 @@ struct cj_plan_s {
     hipEvent_t ev[2] = {nullptr, nullptr};   // bracket the plain sweeps of a cycle
     size_t workspace_bytes() const {
         return 3 * L.elems * sizeof(double) + (size_t)s.M * sizeof(double) +
-               ((size_t)T.count() + 64) * sizeof(double);
+               ((size_t)n_partials() + 64) * sizeof(double);
     }
+    int n_partials() const { return T.count() > TK.count() ? T.count() : TK.count(); }
 };
 
 namespace {
@@ -111,7 +114,7 @@ cj_status ensure_device(cj_plan_s* p, hipStream_t stream) {
     if (e == hipSuccess) e = hipMalloc((void**)&p->B, bytes);
     if (e == hipSuccess) e = hipMalloc((void**)&p->G, bytes);
     if (e == hipSuccess) e = hipMalloc((void**)&p->W, (size_t)p->s.M * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void**)&p->part, (size_t)p->T.count() * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&p->part, (size_t)p->n_partials() * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&p->scalar, 64 * sizeof(double));
     if (e == hipSuccess) e = hipHostMalloc((void**)&p->host_slot, 64 * sizeof(double), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreate(&p->ev[0]);
@@ -149,13 +152,34 @@ cj_status stage_in(cj_plan_s* p, const double* f, const double* u, hipStream_t s
     return read_sum(p, p->T.count(), stream, g2);
 }
 
-// Enqueues sweeps [first, first + n) of the cyclic schedule, starting from *cur.
+// Enqueues sweeps [first, first + n) of the cyclic schedule, starting from *cur,
+// in launches of K sweeps (single sweeps where a launch would run past the end
+// of the cycle or of the range).  If norm_parts != nullptr the first launch
+// also produces the residual partials of its input and *norm_parts receives
+// their count.  *launches counts the launches.
 cj_status enqueue_sweeps(cj_plan_s* p, long long first, long long n, double** cur, double** nxt,
-                         hipStream_t stream) {
-    for (long long k = 0; k < n; ++k) {
-        const int widx = (int)((first + k) % p->s.M);
-        CJ_HIP(cj::launch_sweep(p->s.stencil, p->L, p->T, *cur, *nxt, p->G, p->W, widx, nullptr, stream));
+                         hipStream_t stream, int* norm_parts = nullptr, long long* launches = nullptr) {
+    const long long M = p->s.M;
+    bool norm = norm_parts != nullptr;
+    while (n > 0) {
+        const int w0 = (int)(first % M);
+        long long k = p->K;
+        if (k > n) k = n;
+        if (k > M - w0) k = M - w0;
+        double* part = norm ? p->part : nullptr;
+        if (k == p->K && p->K > 1) {
+            CJ_HIP(cj::launch_sweepk(p->s.stencil, p->K, p->L, p->TK, *cur, *nxt, p->G, p->W, w0, part, stream));
+            if (norm) *norm_parts = p->TK.count();
+        } else {
+            k = 1;
+            CJ_HIP(cj::launch_sweep(p->s.stencil, p->L, p->T, *cur, *nxt, p->G, p->W, w0, part, stream));
+            if (norm) *norm_parts = p->T.count();
+        }
+        norm = false;
+        if (launches) ++*launches;
         std::swap(*cur, *nxt);
+        first += k;
+        n -= k;
     }
     return CJ_OK;
 }
@@ -179,6 +203,9 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol, const cj_o
         if (r != 0) return fail(CJ_ERR_ARG, "reserved option fields must be zero");
     if (o.max_cycles < 0 || o.sweeps_per_launch < 0 || o.tile_rows < 0)
         return fail(CJ_ERR_ARG, "negative option");
+    if (o.sweeps_per_launch > 1 && !cj::sweepk_supported(stencil, o.sweeps_per_launch))
+        return fail(CJ_ERR_ARG, "sweeps_per_launch not available for this stencil "
+                                "(5/9-point: 1, 2, 3, 4, 6, 8; 17-point: 1, 2, 3, 4)");
     cj_plan_s* p = new (std::nothrow) cj_plan_s();
     if (!p) return fail(CJ_ERR_NOMEM, "host allocation");
     std::string err;
@@ -189,7 +216,12 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol, const cj_o
     p->opt = o;
     p->max_cycles = o.max_cycles > 0 ? o.max_cycles : p->s.cycles_pred + 4;
     p->L = cj::make_layout(nx, ny);
-    p->T = cj::make_tiles(nx, ny, o.tile_rows);
+    const int R = stencil == 17 ? 2 : 1;
+    // default depths from measurements at 8192^2 on MI355X (9-point: K = 8 is 3.2x the
+    // single-sweep rate; 17-point: K = 3, deeper windows exhaust the registers)
+    p->K = o.sweeps_per_launch > 0 ? o.sweeps_per_launch : (stencil == 17 ? 3 : 8);
+    p->T = cj::make_tiles(nx, ny, p->K == 1 ? o.tile_rows : 0);
+    if (p->K > 1) p->TK = cj::make_tiles_k(nx, ny, p->K, R, o.tile_rows);
     p->D = centre_over_s(stencil) / (p->s.h * p->s.h);
     *out = p;
     return CJ_OK;
@@ -208,6 +240,15 @@ cj_status cj_plan_info(cj_plan_t p, double* kmin, double* kmax, int* M, int* cyc
     if (cycles_pred) *cycles_pred = p->s.cycles_pred;
     if (weights_host) *weights_host = p->s.w.data();
     if (workspace_bytes) *workspace_bytes = p->workspace_bytes();
+    return CJ_OK;
+}
+
+cj_status cj_plan_launch_info(cj_plan_t p, int* sweeps_per_launch, int* tile_rows, int* workgroups) {
+    if (!p) return fail(CJ_ERR_ARG, "plan is NULL");
+    const cj::Tiles& T = p->K > 1 ? p->TK : p->T;
+    if (sweeps_per_launch) *sweeps_per_launch = p->K;
+    if (tile_rows) *tile_rows = T.rows;
+    if (workgroups) *workgroups = T.count();
     return CJ_OK;
 }
 
@@ -243,45 +284,50 @@ cj_status cj_solve(cj_plan_t p, const double* f, double* u, void* stream_, cj_re
     double prev = 0.0;
     cj_status outcome = CJ_OK;
     int c = 0;
-    bool timed = false;   // events ev[0], ev[1] bracket the previous cycle's plain sweeps
+    bool timed = false;   // events ev[0], ev[1] bracket the previous cycle's plain launches
+    long long timed_launches = 0;
+    // the launch that also yields the norm is a single launch (K sweeps, or one
+    // sweep when the cycle is shorter than K), so that its input stays intact
+    const long long k0 = p->K <= M ? p->K : 1;
     for (;;) {
-        // first sweep of the next cycle, fused with the residual of its input
-        hipError_t e = cj::launch_sweep(p->s.stencil, p->L, p->T, cur, nxt, p->G, p->W, 0, p->part, stream);
-        if (e != hipSuccess) return finish(fail(CJ_ERR_HIP, hipGetErrorString(e)));
+        // first launch of the next cycle, fused with the residual of its input
+        int nparts = 0;
+        if ((st = enqueue_sweeps(p, 0, k0, &cur, &nxt, stream, &nparts)) != CJ_OK) return finish(st);
         double r2 = 0.0;
-        if ((st = read_sum(p, p->T.count(), stream, &r2)) != CJ_OK) return finish(st);
+        if ((st = read_sum(p, nparts, stream, &r2)) != CJ_OK) return finish(st);
         if (timed) {
             float ms = 0.0f;
             CJ_HIP(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
             r.sweep_seconds += 1e-3 * (double)ms;
-            r.sweep_launches += M - 1;
+            r.sweep_launches += timed_launches;
             timed = false;
         }
         const double rr = std::sqrt(r2) / gnorm;
         r.rel_residual = rr;
+        bool stop = true;
         if (!std::isfinite(rr)) {
             outcome = fail(CJ_ERR_NONFINITE, "residual is not finite (u has a NaN or Inf)");
-            break;
-        }
-        if (rr <= p->s.tol) {
+        } else if (rr <= p->s.tol) {
             outcome = CJ_OK;
-            break;
-        }
-        if (c >= 1 && c >= p->s.cycles_pred && rr > 0.5 * prev) {
+        } else if (c >= 1 && c >= p->s.cycles_pred && rr > 0.5 * prev) {
             outcome = CJ_STAGNATED;
             r.floor_estimate = rr < prev ? rr : prev;
             g_last_error = "residual stagnated above tol (FP64 floor)";
-            break;
-        }
-        if (c >= p->max_cycles) {
+        } else if (c >= p->max_cycles) {
             outcome = fail(CJ_ERR_NOT_CONVERGED, "max_cycles reached");
+        } else {
+            stop = false;
+        }
+        if (stop) {
+            std::swap(cur, nxt);   // the answer is the input of the launch just made
             break;
         }
         prev = rr;
-        std::swap(cur, nxt);
-        if (M > 1) {
+        if (M > k0) {
+            timed_launches = 0;
             CJ_HIP(hipEventRecord(p->ev[0], stream));
-            if ((st = enqueue_sweeps(p, 1, M - 1, &cur, &nxt, stream)) != CJ_OK) return finish(st);
+            if ((st = enqueue_sweeps(p, k0, M - k0, &cur, &nxt, stream, nullptr, &timed_launches)) != CJ_OK)
+                return finish(st);
             CJ_HIP(hipEventRecord(p->ev[1], stream));
             timed = true;
         }

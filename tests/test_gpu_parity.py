@@ -100,6 +100,44 @@ def test_sweep_prefix_from_rough_guess(torch_cuda, st):
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+BLOCKED = [(5, 2), (5, 3), (5, 4), (5, 6), (5, 8), (9, 2), (9, 3), (9, 4), (9, 6), (9, 8),
+           (17, 2), (17, 3), (17, 4)]
+
+
+@pytest.mark.parametrize("st,K", BLOCKED)
+@pytest.mark.parametrize("nx,ny,rows", [(517, 203, 16), (1, 1, 0), (3, 2, 0), (40, 7, 0), (250, 300, 64)])
+def test_blocked_sweeps_match_single_sweeps_bitwise(torch_cuda, st, K, nx, ny, rows):
+    """K sweeps per launch (temporal blocking) give the same bits as K launches of
+    one sweep, across strips, tile seams, ragged edges and cycle ends; and both
+    match the oracle."""
+    torch = torch_cuda
+    f = inputs.gaussian_bumps_rhs(nx, ny, seed=21)
+    u0 = inputs.random_field(nx, ny, seed=22)
+    n = 2 * 8 + 3
+    ref1 = _dev(torch, u0)
+    cj.sweeps(cj.plan(nx, ny, st, 1e-6, M=8, sweeps_per_launch=1), _dev(torch, f), ref1, n)
+    pk = cj.plan(nx, ny, st, 1e-6, M=8, sweeps_per_launch=K, tile_rows=rows)
+    assert pk.sweeps_per_launch == K
+    uk = _dev(torch, u0)
+    cj.sweeps(pk, _dev(torch, f), uk, n)
+    assert np.array_equal(_host(uk), _host(ref1))
+    ref = cjm.run_sweeps(f, nx, ny, st, 1e-6, n, M=8, u0=u0)
+    assert np.abs(_host(uk) - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("st,K", [(9, 1), (9, 8), (5, 1), (17, 1), (17, 4)])
+def test_full_solve_parity_launch_depths(torch_cuda, st, K):
+    torch = torch_cuda
+    nx, ny, tol = 211, 143, 1e-10
+    f = inputs.gaussian_bumps_rhs(nx, ny, seed=77)
+    ref = cjm.solve(f, nx, ny, st, tol)
+    p = cj.plan(nx, ny, st, tol, sweeps_per_launch=K)
+    u = torch.zeros(ny, nx, dtype=torch.float64, device="cuda")
+    r = cj.solve(p, _dev(torch, f), u)
+    assert (r["status"], r["cycles"]) == (ref["status"], ref["cycles"])
+    assert _rel(_host(u), ref["u"]) <= REL_L2
+
+
 def test_zero_sweeps_round_trip_is_exact(torch_cuda):
     torch = torch_cuda
     for st in (5, 9, 17):
