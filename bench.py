@@ -130,6 +130,11 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=8192, help="interior nodes per axis")
+    ap.add_argument("--ny", type=int, default=None, help="interior nodes in y (default: --n)")
+    ap.add_argument("--precision", choices=("f64", "f32-refine"), default="f64",
+                    help="f64: the plain FP64 solve; f32-refine: FP32 sweeps inside FP64 refinement")
+    ap.add_argument("--reference-f64", action="store_true",
+                    help="with --precision f32-refine: also run one plain FP64 solve and report the difference")
     ap.add_argument("--stencil", type=int, default=9, choices=(5, 9, 17))
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--seed", type=int, default=None, help="RHS seed (default 1705 + stencil)")
@@ -152,14 +157,16 @@ def main():
     from paper_1705_00103_amd import cj, inputs
 
     n, st, tol = args.n, args.stencil, args.tol
+    ny = args.n if args.ny is None else args.ny
     if args.traffic_probe:
         traffic_probe(n, st, tol)
         return
+    mixed = args.precision == "f32-refine"
     seed = 1705 + st if args.seed is None else args.seed
-    f = inputs.gaussian_bumps_rhs(n, n, seed=seed)
+    f = inputs.gaussian_bumps_rhs(n, ny, seed=seed)
     fd = torch.from_numpy(f).to("cuda")
-    u = torch.zeros(n, n, dtype=torch.float64, device="cuda")
-    p = cj.plan(n, n, st, tol)
+    u = torch.zeros(ny, n, dtype=torch.float64, device="cuda")
+    p = cj.plan(n, ny, st, tol, precision=cj.F32_REFINE if mixed else cj.F64)
 
     for _ in range(args.warmup):
         u.zero_()
@@ -179,26 +186,37 @@ def main():
     t1 = time.perf_counter()
 
     ms_per_step = (t1 - t0) / args.steps * 1e3
-    updates_per_step = float(n) * n * sum(r["sweeps"] for r in res) / args.steps
+    updates_per_step = float(n) * ny * sum(r["sweeps"] for r in res) / args.steps
     value = updates_per_step / (ms_per_step * 1e-3)
 
     sweep_s = sum(r["sweep_seconds"] for r in res)
     launches = sum(r["sweep_launches"] for r in res)
     K = p.sweeps_per_launch
+    bpu = 12.0 if mixed else BYTES_PER_UPDATE
     roofline = None
     if launches > 0:
         avg = sweep_s / launches
-        algo = BYTES_PER_UPDATE * K * n * n
+        algo = bpu * K * n * ny
         achieved = algo / avg / 1e9
-        traffic = measured_traffic(n, st)
+        traffic = None if (mixed or ny != n) else measured_traffic(n, st)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                    "kernel": "sweepk_kernel<%d, K=%d, no-norm>" % (st, K), "sweeps_per_launch": K,
+                    "kernel": "sweepk_kernel<%s, %d, K=%d, no-norm>" % ("float" if mixed else "double", st, K),
+                    "sweeps_per_launch": K,
                     "avg_launch_us": round(avg * 1e6, 2), "algorithmic_bytes_per_launch": algo,
-                    "compulsory_hbm_bytes_per_launch": BYTES_PER_UPDATE * n * n}
+                    "compulsory_hbm_bytes_per_launch": bpu * n * ny}
         if traffic:
             roofline["traffic_gbs"] = round(traffic / avg / 1e9, 1)
-    single = single_sweep_reference(cj, fd, n, st, tol)
+    single = None if (mixed or ny != n) else single_sweep_reference(cj, fd, n, st, tol)
+    ref64 = None
+    if mixed and args.reference_f64:
+        p64 = cj.plan(n, ny, st, tol)
+        u64 = torch.zeros_like(u)
+        r64 = cj.solve(p64, fd, u64)
+        ref64 = {"rel_l2_vs_f64_solve": float(torch.linalg.norm(u - u64) / torch.linalg.norm(u64)),
+                 "f64_status": r64["status"], "f64_rel_residual": r64["rel_residual"],
+                 "f64_seconds": r64["seconds"]}
+        p64.destroy()
 
     lat_ms = sorted(x * 1e3 for x in lat)
     p50 = float(np.percentile(lat_ms, 50))
@@ -206,7 +224,7 @@ def main():
     last = res[-1]
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not mixed and ny == n:
         cpu = cpu_baseline(f, n, st, tol, args.cpu_seconds)
 
     out = {
@@ -220,11 +238,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
         "config": {
-            "workload": "cjm-fp64-%dpt-%dx%d-bumps16-tol%g" % (st, n, n, tol),
-            "nx": n, "ny": n, "stencil": st, "tol": tol, "rhs_seed": seed, "M": p.M,
+            "workload": "cjm-%s-%dpt-%dx%d-bumps16-tol%g" % ("f32refine" if mixed else "fp64", st, n, ny, tol),
+            "nx": n, "ny": ny, "stencil": st, "tol": tol, "rhs_seed": seed, "M": p.M,
             "cycles_pred": p.cycles_pred, "sweeps_per_launch": K, "tile_rows": p.tile_rows,
             "parallelism": "single-gpu",
         },
@@ -237,6 +255,7 @@ def main():
         "effective_tol": last["rel_residual"] if last["status"] == "stagnated" else tol,
         "roofline": roofline,
         "single_sweep_reference": single,
+        "f64_reference": ref64,
         "cpu_baseline": cpu,
     }
     if cpu is not None:

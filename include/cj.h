@@ -61,26 +61,41 @@ typedef enum { CJ_STENCIL_5 = 5, CJ_STENCIL_9 = 9, CJ_STENCIL_17 = 17 } cj_stenc
 
 typedef enum { CJ_BC_DIRICHLET0 = 0 } cj_bc;
 
+/* Working precision of a plan.
+ * CJ_PRECISION_F64: FP64 sweeps, the method as stated (§2.1).
+ * CJ_PRECISION_F32_REFINE: iterative refinement; every outer step forms the
+ *   residual r = f - A u in FP64, approximately solves A d = r with one cycle
+ *   of FP32 weighted sweeps from d = 0 (the same Chebyshev schedule, weights
+ *   rounded to FP32), and adds d to u in FP64.  The stopping test is the FP64
+ *   relative residual.  Each FP32 sweep moves half the bytes of an FP64 one;
+ *   the contraction per outer step is limited to about eps32 * kmax / kmin,
+ *   so large grids may stagnate (reported as CJ_STAGNATED). */
+typedef enum { CJ_PRECISION_F64 = 0, CJ_PRECISION_F32_REFINE = 1 } cj_precision;
+
 /* Tuning and schedule options for cj_plan_ex.  Zero means "automatic". */
 typedef struct {
     int    M;                  /* cycle length; 0 = the power of two 2^p that minimises
                                   (predicted cycles x M), ties to the smaller; else a
                                   power of two, 1 <= M <= 2^24 */
-    int    max_cycles;         /* 0 = predicted cycles + 4 */
+    int    max_cycles;         /* 0 = predicted cycles + 4 (CJ_PRECISION_F32_REFINE: the
+                                  maximum number of outer steps, 0 = 50) */
     int    sweeps_per_launch;  /* temporal-blocking depth K of the sweep kernel: sweeps fused
                                   into one launch; 0 = automatic (8 for the 5- and 9-point
                                   stencils, 3 for 17 points); 1, 2, 3, 4, 6, 8 (5/9-point)
                                   or 1, 2, 3, 4 (17-point) */
     int    tile_rows;          /* rows per workgroup tile of the sweep kernel, 0 = auto */
     double h;                  /* mesh spacing; 0 = 1 / max(nx + 1, ny + 1) */
-    int    reserved[8];        /* must be zero */
+    int    precision;          /* cj_precision; 0 = CJ_PRECISION_F64 */
+    int    inner_M;            /* CJ_PRECISION_F32_REFINE: inner cycle length (a power of
+                                  two); 0 = the automatic M.  Must be 0 otherwise. */
+    int    reserved[6];        /* must be zero */
 } cj_options;
 
 /* Outcome of a solve. */
 typedef struct {
     int       status;          /* the cj_status returned */
-    int       cycles;          /* completed weight cycles */
-    long long sweeps;          /* cycles * M */
+    int       cycles;          /* completed weight cycles (refinement: outer steps) */
+    long long sweeps;          /* cycles * M (refinement: FP32 sweeps) */
     double    rel_residual;    /* ||f - A u||_2 / ||f||_2 of the returned u */
     double    floor_estimate;  /* on CJ_STAGNATED: the residual level successive cycles
                                   stopped improving on; 0 otherwise */
@@ -106,7 +121,9 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol,
                      const cj_options* opt, cj_plan_t* out);
 
 /* Reads a plan.  Any output pointer may be NULL.  *weights_host points to the
- * plan's M weights in applied order (owned by the plan, valid until destroy).
+ * plan's M weights in applied order (owned by the plan, valid until destroy);
+ * for CJ_PRECISION_F32_REFINE plans M, cycles_pred and the weights are those
+ * of the inner FP32 cycle.
  * *workspace_bytes is the device memory cj_solve allocates on first use:
  * two padded iterates, the padded scaled right-hand side, the weights and
  * the reduction buffers. */
@@ -133,7 +150,9 @@ cj_status cj_solve(cj_plan_t p, const double* f, double* u, void* stream, cj_res
 
 /* Applies the first n_sweeps weighted sweeps of the plan's schedule (weights
  * taken cyclically) to the guess u, with no residual test; u is overwritten.
- * Same kernels and launch configuration as cj_solve.  n_sweeps >= 0. */
+ * Same kernels and launch configuration as cj_solve.  n_sweeps >= 0.
+ * CJ_PRECISION_F32_REFINE plans sweep in FP32: u and D^{-1} f are rounded to
+ * FP32, the sweeps run in FP32 and the result is widened back. */
 cj_status cj_sweeps(cj_plan_t p, const double* f, double* u, long long n_sweeps, void* stream);
 
 /* *rel_residual = ||f - A u||_2 / ||f||_2 (0 when f = 0), FP64 with a

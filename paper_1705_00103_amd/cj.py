@@ -25,6 +25,9 @@ CJ_ERR_NOT_CONVERGED = -4
 CJ_ERR_NONFINITE = -5
 CJ_ERR_DEVICE = -6
 
+F64 = 0             # CJ_PRECISION_F64
+F32_REFINE = 1      # CJ_PRECISION_F32_REFINE
+
 STATUS_NAMES = {
     CJ_OK: "ok", CJ_STAGNATED: "stagnated", CJ_ERR_ARG: "arg", CJ_ERR_NOMEM: "nomem",
     CJ_ERR_HIP: "hip", CJ_ERR_NOT_CONVERGED: "not_converged", CJ_ERR_NONFINITE: "nonfinite",
@@ -39,7 +42,8 @@ EXPORTS = ("cj_options_init", "cj_plan", "cj_plan_ex", "cj_plan_info", "cj_plan_
 class Options(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int), ("max_cycles", ctypes.c_int),
                 ("sweeps_per_launch", ctypes.c_int), ("tile_rows", ctypes.c_int),
-                ("h", ctypes.c_double), ("reserved", ctypes.c_int * 8)]
+                ("h", ctypes.c_double), ("precision", ctypes.c_int), ("inner_M", ctypes.c_int),
+                ("reserved", ctypes.c_int * 6)]
 
 
 class Result(ctypes.Structure):
@@ -121,11 +125,13 @@ class Plan:
     """Owns a cj_plan_t.  Attributes mirror cj_plan_info."""
 
     def __init__(self, nx, ny, stencil=9, tol=1e-10, M=0, max_cycles=0, sweeps_per_launch=0,
-                 tile_rows=0, h=0.0, bc=0):
+                 tile_rows=0, h=0.0, bc=0, precision=F64, inner_M=0):
         L = lib()
         o = Options()
         L.cj_options_init(ctypes.byref(o))
         o.M, o.max_cycles, o.sweeps_per_launch, o.tile_rows, o.h = M, max_cycles, sweeps_per_launch, tile_rows, h
+        o.precision, o.inner_M = precision, inner_M
+        self.precision = precision
         handle = ctypes.c_void_p()
         _check(L.cj_plan_ex(nx, ny, stencil, bc, tol, ctypes.byref(o), ctypes.byref(handle)), "cj_plan_ex")
         self._h = handle

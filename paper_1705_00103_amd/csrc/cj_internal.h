@@ -28,20 +28,21 @@ bool make_schedule(int stencil, int nx, int ny, double tol, double h, int M_requ
 // ---------------------------------------------------------------- device layout
 
 // Padded, pitched storage of a grid function: node (x, y) for
-// -1 <= x <= nx + 2, -1 <= y <= ny + 2 lives at (y + 1) * pitch + (x + kXOff).
-// kXOff puts the first interior column x = 1 on a 128-byte boundary.  The ring
-// x in {0, nx+1}, y in {0, ny+1} holds the Dirichlet zeros; the outer ring
-// x in {-1, nx+2}, y in {-1, ny+2} holds the odd reflection of the interior
-// (read by the 17-point stencil only).
-constexpr int kXOff = 15;
+// -1 <= x <= nx + 2, -1 <= y <= ny + 2 lives at (y + 1) * pitch + (x + xoff),
+// xoff = 128 / element_bytes - 1, which puts the first interior column x = 1
+// on a 128-byte boundary.  The ring x in {0, nx+1}, y in {0, ny+1} holds the
+// Dirichlet zeros; the outer ring x in {-1, nx+2}, y in {-1, ny+2} holds the
+// odd reflection of the interior (read by the 17-point stencil only).
+__host__ __device__ constexpr int xoff_of(int elem_bytes) { return 128 / elem_bytes - 1; }
 
 struct Layout {
     int nx = 0, ny = 0;
-    int pitch = 0;          // doubles per stored row
-    size_t elems = 0;       // doubles per padded array
+    int elem_bytes = 8;
+    int pitch = 0;          // elements per stored row
+    size_t elems = 0;       // elements per padded array
 };
 
-Layout make_layout(int nx, int ny);
+Layout make_layout(int nx, int ny, int elem_bytes);
 
 // Launch geometry of the tile kernels (sweeps, residual, stage-in).
 struct Tiles {
@@ -79,13 +80,31 @@ hipError_t launch_stage_out(const Layout& L, const double* A, double* u, hipStre
 hipError_t launch_sweep(int stencil, const Layout& L, const Tiles& T, const double* uin,
                         double* uout, const double* g, const double* w, int widx,
                         double* part, hipStream_t stream);
+// The same sweep in FP32 (part must be nullptr).
+hipError_t launch_sweep(int stencil, const Layout& L, const Tiles& T, const float* uin,
+                        float* uout, const float* g, const float* w, int widx,
+                        double* part, hipStream_t stream);
 
 // K sweeps in one launch (weights w[widx .. widx+K-1]), bit-identical to K
 // launch_sweep calls.  If part != nullptr, per-tile partial sums of r^2 of uin
 // go to part[0 .. tiles.count()).  T must come from make_tiles_k.
-bool sweepk_supported(int stencil, int K);
+bool sweepk_supported(int stencil, int K, int elem_bytes);
 hipError_t launch_sweepk(int stencil, int K, const Layout& L, const Tiles& T, const double* uin, double* uout,
                          const double* g, const double* w, int widx, double* part, hipStream_t stream);
+// The same in FP32 (part must be nullptr).
+hipError_t launch_sweepk(int stencil, int K, const Layout& L, const Tiles& T, const float* uin, float* uout,
+                         const float* g, const float* w, int widx, double* part, hipStream_t stream);
+
+// Iterative refinement: r32 <- (float)(g - D^{-1}A u) and d32 <- 0 (interior
+// and reflected ring), per-tile partials of r^2 (FP64) into part.  L32 is the
+// FP32 layout of the same grid; T the single-sweep tile geometry.
+hipError_t launch_ir_residual(int stencil, const Layout& L, const Layout& L32, const Tiles& T, const double* u,
+                              const double* g, float* r32, float* d32, double* part, hipStream_t stream);
+// u += (double)d over the padded frame.
+hipError_t launch_ir_correct(const Layout& L, const Layout& L32, double* u, const float* d, hipStream_t stream);
+// Padded-frame conversions between the FP64 and FP32 layouts.
+hipError_t launch_to_f32(const Layout& L, const Layout& L32, const double* src, float* dst, hipStream_t stream);
+hipError_t launch_from_f32(const Layout& L, const Layout& L32, const float* src, double* dst, hipStream_t stream);
 
 // Per-tile partial sums of r^2 of u (read-only).
 hipError_t launch_residual(int stencil, const Layout& L, const Tiles& T, const double* u,

@@ -1,23 +1,38 @@
 // HIP kernels of libcj.so for gfx950 (MI355X): stage-in/out, the weighted
-// Chebyshev-Jacobi sweep, the residual norm and the stencil apply.
+// Chebyshev-Jacobi sweep (one sweep per launch, or K sweeps per launch with
+// temporal blocking), the residual norm, the stencil apply, and the FP32 /
+// FP64 pieces of iterative refinement.
 //
 // All kernels work on the padded, pitched layout described in cj_internal.h.
-// The sweep is HBM-bound (24 bytes and 8-24 flops per grid-point update), so
-// the kernels are organised around memory traffic: one wave64 lane per grid
-// column, marching up the rows of its tile and keeping the (2R+1) rows of the
-// stencil window in registers, so that every value of u is fetched from HBM
-// once per sweep and the row re-reads of the window hit registers.  Row loads
-// of a wave are 64 consecutive doubles (512 B), aligned on the interior.
+// A sweep is HBM-bound (24 bytes in FP64, 12 in FP32, and 8-24 flops per
+// grid-point update), so the kernels are organised around memory traffic: one
+// wave64 lane per grid column, marching up the rows of its tile and keeping
+// the (2R+1) rows of the stencil window in registers, so that every value of
+// u is fetched from HBM once per sweep and the row re-reads of the window hit
+// registers.  Row loads of a wave are 64 consecutive elements, aligned on the
+// interior.
 //
-// Arithmetic is written with explicit fma() and compiled with
-// -ffp-contract=off, so that every kernel that evaluates the update performs
-// exactly the same operations in the same order and produces the same bits.
+// Arithmetic is written with explicit fma and compiled with
+// -ffp-contract=off, so that every kernel that evaluates the update in a
+// given precision performs exactly the same operations in the same order and
+// produces the same bits.
 #include <hip/hip_runtime.h>
 
 #include "cj_internal.h"
 
 namespace cj {
 namespace {
+
+// ------------------------------------------------------------ element types
+
+template <typename T> __device__ __forceinline__ T fmat(T a, T b, T c);
+template <> __device__ __forceinline__ double fmat<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <> __device__ __forceinline__ float fmat<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+template <typename T>
+__device__ __forceinline__ size_t at(int pitch, int x, int y) {
+    return (size_t)(y + 1) * (size_t)pitch + (size_t)(x + xoff_of(sizeof(T)));
+}
 
 // ------------------------------------------------------------ stencils
 // The update in normalised form.  With c_hat = c / |c_centre| and
@@ -30,42 +45,43 @@ namespace {
 //     9-point : 4/20 axis, 1/20 diagonal
 //     17-point: 64/300 axis ring 1, -4/300 axis ring 2,
 //               16/300 diagonal ring 1, -1/300 diagonal ring 2.
+// v[dy + R][dx + R] holds u(x + dx, y + dy); nsum returns t.
 
 template <int ST> struct Stencil;
-template <> struct Stencil<5>  { static constexpr int R = 1; };
-template <> struct Stencil<9>  { static constexpr int R = 1; };
-template <> struct Stencil<17> { static constexpr int R = 2; };
 
-// v[dy + R][dx + R] holds u(x + dx, y + dy).  Returns t.
-template <int ST>
-__device__ __forceinline__ double neighbour_sum(const double (&v)[2 * Stencil<ST>::R + 1][2 * Stencil<ST>::R + 1]);
+template <> struct Stencil<5> {
+    static constexpr int R = 1;
+    template <typename T> __device__ static __forceinline__ T nsum(const T (&v)[3][3]) {
+        const T axis = (v[1][0] + v[1][2]) + (v[0][1] + v[2][1]);
+        return T(0.25) * axis;
+    }
+};
 
-template <>
-__device__ __forceinline__ double neighbour_sum<5>(const double (&v)[3][3]) {
-    const double axis = (v[1][0] + v[1][2]) + (v[0][1] + v[2][1]);
-    return 0.25 * axis;
-}
+template <> struct Stencil<9> {
+    static constexpr int R = 1;
+    template <typename T> __device__ static __forceinline__ T nsum(const T (&v)[3][3]) {
+        const T axis = (v[1][0] + v[1][2]) + (v[0][1] + v[2][1]);
+        const T diag = (v[0][0] + v[2][2]) + (v[2][0] + v[0][2]);
+        return fmat<T>(T(0.2), axis, T(0.05) * diag);
+    }
+};
 
-template <>
-__device__ __forceinline__ double neighbour_sum<9>(const double (&v)[3][3]) {
-    const double axis = (v[1][0] + v[1][2]) + (v[0][1] + v[2][1]);
-    const double diag = (v[0][0] + v[2][2]) + (v[2][0] + v[0][2]);
-    return fma(0.2, axis, 0.05 * diag);
-}
+template <> struct Stencil<17> {
+    static constexpr int R = 2;
+    template <typename T> __device__ static __forceinline__ T nsum(const T (&v)[5][5]) {
+        const T axis1 = (v[2][1] + v[2][3]) + (v[1][2] + v[3][2]);
+        const T axis2 = (v[2][0] + v[2][4]) + (v[0][2] + v[4][2]);
+        const T diag1 = (v[1][1] + v[3][3]) + (v[3][1] + v[1][3]);
+        const T diag2 = (v[0][0] + v[4][4]) + (v[4][0] + v[0][4]);
+        const T a1 = T(64.0 / 300.0), a2 = T(-4.0 / 300.0);
+        const T d1 = T(16.0 / 300.0), d2 = T(-1.0 / 300.0);
+        return fmat<T>(a1, axis1, fmat<T>(a2, axis2, fmat<T>(d1, diag1, d2 * diag2)));
+    }
+};
 
-template <>
-__device__ __forceinline__ double neighbour_sum<17>(const double (&v)[5][5]) {
-    const double axis1 = (v[2][1] + v[2][3]) + (v[1][2] + v[3][2]);
-    const double axis2 = (v[2][0] + v[2][4]) + (v[0][2] + v[4][2]);
-    const double diag1 = (v[1][1] + v[3][3]) + (v[3][1] + v[1][3]);
-    const double diag2 = (v[0][0] + v[4][4]) + (v[4][0] + v[0][4]);
-    constexpr double a1 = 64.0 / 300.0, a2 = -4.0 / 300.0;
-    constexpr double d1 = 16.0 / 300.0, d2 = -1.0 / 300.0;
-    return fma(a1, axis1, fma(a2, axis2, fma(d1, diag1, d2 * diag2)));
-}
-
-__device__ __forceinline__ size_t at(int pitch, int x, int y) {
-    return (size_t)(y + 1) * (size_t)pitch + (size_t)(x + kXOff);
+template <typename T, int ST>
+__device__ __forceinline__ T neighbour_sum(const T (&v)[2 * Stencil<ST>::R + 1][2 * Stencil<ST>::R + 1]) {
+    return Stencil<ST>::template nsum<T>(v);
 }
 
 // Hardware dispatches workgroup b to XCD b % 8.  Give every XCD a contiguous
@@ -98,22 +114,21 @@ __device__ __forceinline__ double block_sum(double v) {
 // Stores u'(x, y) with a streaming (non-temporal) store: the new iterate is not
 // read again before it has left the caches.  For the 17-point stencil the odd
 // reflections on the outer ring are kept up to date as well.
-template <int ST>
-__device__ __forceinline__ void store_update(double* __restrict__ uout, int pitch, int nx, int ny, int x, int y,
-                                             double un) {
-    __builtin_nontemporal_store(un, uout + at(pitch, x, y));
+template <typename T, int ST>
+__device__ __forceinline__ void store_update(T* __restrict__ uout, int pitch, int nx, int ny, int x, int y, T un) {
+    __builtin_nontemporal_store(un, uout + at<T>(pitch, x, y));
     if (ST == 17) {
-        if (x == 1) uout[at(pitch, -1, y)] = -un;
-        if (x == nx) uout[at(pitch, nx + 2, y)] = -un;
+        if (x == 1) uout[at<T>(pitch, -1, y)] = -un;
+        if (x == nx) uout[at<T>(pitch, nx + 2, y)] = -un;
         if (y == 1) {
-            uout[at(pitch, x, -1)] = -un;
-            if (x == 1) uout[at(pitch, -1, -1)] = un;
-            if (x == nx) uout[at(pitch, nx + 2, -1)] = un;
+            uout[at<T>(pitch, x, -1)] = -un;
+            if (x == 1) uout[at<T>(pitch, -1, -1)] = un;
+            if (x == nx) uout[at<T>(pitch, nx + 2, -1)] = un;
         }
         if (y == ny) {
-            uout[at(pitch, x, ny + 2)] = -un;
-            if (x == 1) uout[at(pitch, -1, ny + 2)] = un;
-            if (x == nx) uout[at(pitch, nx + 2, ny + 2)] = un;
+            uout[at<T>(pitch, x, ny + 2)] = -un;
+            if (x == 1) uout[at<T>(pitch, -1, ny + 2)] = un;
+            if (x == nx) uout[at<T>(pitch, nx + 2, ny + 2)] = un;
         }
     }
 }
@@ -122,13 +137,13 @@ __device__ __forceinline__ void store_update(double* __restrict__ uout, int pitc
 // One lane per column x of a tile of width blockDim.x and `rows` rows.  The
 // lane keeps the window rows y-R .. y+R in registers and loads one new row
 // (2R+1 columns) per output row.  WRITE: store the update; NORM: accumulate
-// r^2 of the input iterate.
+// r^2 of the input iterate (FP64 only).
 
-template <int ST, bool WRITE, bool NORM>
-__global__ __launch_bounds__(256) void sweep_kernel(
-    const double* __restrict__ uin, double* __restrict__ uout, const double* __restrict__ g,
-    const double* __restrict__ w, int widx, int nx, int ny, int pitch, int tiles_x, int rows,
-    double* __restrict__ part) {
+template <typename T, int ST, bool WRITE, bool NORM>
+__global__ __launch_bounds__(256) void sweep_kernel(const T* __restrict__ uin, T* __restrict__ uout,
+                                                    const T* __restrict__ g, const T* __restrict__ w, int widx,
+                                                    int nx, int ny, int pitch, int tiles_x, int rows,
+                                                    double* __restrict__ part) {
     constexpr int R = Stencil<ST>::R;
     constexpr int W = 2 * R + 1;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -138,12 +153,12 @@ __global__ __launch_bounds__(256) void sweep_kernel(
     const int xl = active ? x : nx;   // idle lanes load a valid column and store nothing
     const int y0 = ty * rows + 1;
     const int y1 = min(y0 + rows, ny + 1);
-    const double omega = WRITE ? w[widx] : 0.0;
+    const T omega = WRITE ? w[widx] : T(0);
 
-    double v[W][W];
+    T v[W][W];
 #pragma unroll
     for (int r = 1; r < W; ++r) {
-        const double* p = uin + at(pitch, xl - R, y0 - R + r - 1);
+        const T* p = uin + at<T>(pitch, xl - R, y0 - R + r - 1);
 #pragma unroll
         for (int c = 0; c < W; ++c) v[r][c] = p[c];
     }
@@ -154,14 +169,14 @@ __global__ __launch_bounds__(256) void sweep_kernel(
         for (int r = 0; r < W - 1; ++r)
 #pragma unroll
             for (int c = 0; c < W; ++c) v[r][c] = v[r + 1][c];
-        const double* p = uin + at(pitch, xl - R, y + R);
+        const T* p = uin + at<T>(pitch, xl - R, y + R);
 #pragma unroll
         for (int c = 0; c < W; ++c) v[W - 1][c] = p[c];
-        const double gv = __builtin_nontemporal_load(g + at(pitch, xl, y));
-        const double uc = v[R][R];
-        const double res = (gv + neighbour_sum<ST>(v)) - uc;
-        if (NORM) acc = fma(res, res, acc);
-        if (WRITE && active) store_update<ST>(uout, pitch, nx, ny, x, y, fma(omega, res, uc));
+        const T gv = __builtin_nontemporal_load(g + at<T>(pitch, xl, y));
+        const T uc = v[R][R];
+        const T res = (gv + neighbour_sum<T, ST>(v)) - uc;
+        if (NORM) acc = fmat<double>((double)res, (double)res, acc);
+        if (WRITE && active) store_update<T, ST>(uout, pitch, nx, ny, x, y, fmat<T>(omega, res, uc));
     }
     if (NORM) {
         if (!active) acc = 0.0;
@@ -180,7 +195,8 @@ __global__ __launch_bounds__(256) void sweep_kernel(
 // and every lane keeps a (2R+1) x (2R+1) register window per level, each row
 // tagged with the lane's value of g on that row (the g a level used for a row
 // is the g the next level needs on it).  Only level K is written back, so one
-// launch moves 24 bytes per grid point and performs K updates per point.
+// launch moves one read of u and g and one write of u per grid point and
+// performs K updates per point.
 // Outputs shrink by R columns per level on each side of the strip
 // (256 - 2KR output columns) and the tiles overlap in y by KR rows.
 // The row loop is unrolled by the window height W = 2R+1 so that the window
@@ -190,30 +206,29 @@ __global__ __launch_bounds__(256) void sweep_kernel(
 // Every update evaluates exactly the expression of sweep_kernel on exactly the
 // same values, so K sweeps here give the same bits as K launches of it.
 
-template <int ST, int K>
+template <typename T, int ST, int K>
 struct March {
     static constexpr int R = Stencil<ST>::R;
     static constexpr int W = 2 * R + 1;
     static constexpr int WOUT = 256 - 2 * K * R;
-    double win[K][W][W];   // [level][physical row slot][column x-R .. x+R]
-    double gw[K][W];       // g of the lane's column on each window row
-    double own[K];         // the lane's value of the row a level produced in this step
-    double gused[K];       // the g it used
-    double pre[W];         // prefetched level-0 row
-    double pg;             // and its g
-    int lcol[W];           // level-0 load columns (clamped), with the layout offset
-    int xsrc[W];           // exchange source lanes for the x +- R neighbours
-    int xsgn[W];           // 1, 0 (Dirichlet column) or -1 (reflection), edge workgroups only
+    T win[K][W][W];   // [level][physical row slot][column x-R .. x+R]
+    T gw[K][W];       // g of the lane's column on each window row
+    T own[K];         // the lane's value of the row a level produced in this step
+    T gused[K];       // the g it used
+    T pre[W];         // prefetched level-0 row
+    T pg;             // and its g
+    int lcol[W];      // level-0 load columns (clamped), with the layout offset
+    int xsrc[W];      // exchange source lanes for the x +- R neighbours
+    int xsgn[W];      // 1, 0 (Dirichlet column) or -1 (reflection), edge workgroups only
 };
 
 // One row step with compile-time phase J = t mod W.  Level 0 enters slot J at
 // the start of the step; level s >= 1 enters slot J at its end.
-template <int ST, int K, bool NORM, bool EDGE, int J>
-__device__ __forceinline__ void march_step(March<ST, K>& S, double (*xch)[March<ST, K>::W][256],
-                                           const double* __restrict__ uin, double* __restrict__ uout,
-                                           const double* __restrict__ g, const double (&om)[K], int t,
-                                           int ybase, int x, int xg, bool out_col, int Y0, int Y1, int nx,
-                                           int ny, int pitch, double& acc) {
+template <typename T, int ST, int K, bool NORM, bool EDGE, int J>
+__device__ __forceinline__ void march_step(March<T, ST, K>& S, T (*xch)[March<T, ST, K>::W][256],
+                                           const T* __restrict__ uin, T* __restrict__ uout, const T* __restrict__ g,
+                                           const T (&om)[K], int t, int ybase, int x, int xg, bool out_col, int Y0,
+                                           int Y1, int nx, int ny, int pitch, double& acc) {
     constexpr int R = Stencil<ST>::R;
     constexpr int W = 2 * R + 1;
     const int tid = threadIdx.x;
@@ -223,18 +238,18 @@ __device__ __forceinline__ void march_step(March<ST, K>& S, double (*xch)[March<
     S.gw[0][J] = S.pg;
     {   // prefetch the next level-0 row and its g
         const int yr = min(max(yl + 1, -1), ny + 2);
-        const double* rowp = uin + (size_t)(yr + 1) * (size_t)pitch;
+        const T* rowp = uin + (size_t)(yr + 1) * (size_t)pitch;
 #pragma unroll
         for (int c = 0; c < W; ++c) S.pre[c] = rowp[S.lcol[c]];
-        S.pg = __builtin_nontemporal_load(g + at(pitch, xg, yr));
+        S.pg = __builtin_nontemporal_load(g + at<T>(pitch, xg, yr));
     }
 #pragma unroll
     for (int s = 1; s <= K; ++s) {
         const int Y = yl - (s - 1) - s * R;   // row produced by level s in this step
         // logical window row r (0 = oldest) of level s-1 sits in physical slot
         // (J + 1 + r) % W for level 0 (filled this step) and (J + r) % W above
-        double v[W][W];
-        double gv;
+        T v[W][W];
+        T gv;
 #pragma unroll
         for (int r = 0; r < W; ++r) {
             const int ph = (s == 1) ? (J + 1 + r) % W : (J + r) % W;
@@ -249,7 +264,7 @@ __device__ __forceinline__ void march_step(March<ST, K>& S, double (*xch)[March<
                 const int q = Y - R + r;
                 if (q == 0 || q == ny + 1) {
 #pragma unroll
-                    for (int c = 0; c < W; ++c) v[r][c] = 0.0;
+                    for (int c = 0; c < W; ++c) v[r][c] = T(0);
                 } else if (R == 2 && q == -1 && r + 2 < W) {
 #pragma unroll
                     for (int c = 0; c < W; ++c) v[r][c] = -v[r + 2][c];
@@ -259,16 +274,16 @@ __device__ __forceinline__ void march_step(March<ST, K>& S, double (*xch)[March<
                 }
             }
         }
-        const double uc = v[R][R];
-        const double res = (gv + neighbour_sum<ST>(v)) - uc;
-        const double un = fma(om[s - 1], res, uc);
-        if (NORM && s == 1 && out_col && Y >= Y0 && Y < Y1) acc = fma(res, res, acc);
+        const T uc = v[R][R];
+        const T res = (gv + neighbour_sum<T, ST>(v)) - uc;
+        const T un = fmat<T>(om[s - 1], res, uc);
+        if (NORM && s == 1 && out_col && Y >= Y0 && Y < Y1) acc = fmat<double>((double)res, (double)res, acc);
         if (s < K) {
             xch[s - 1][J][tid] = un;
             S.own[s] = un;
             S.gused[s] = gv;
         } else if (out_col && Y >= Y0 && Y < Y1) {
-            store_update<ST>(uout, pitch, nx, ny, x, Y, un);
+            store_update<T, ST>(uout, pitch, nx, ny, x, Y, un);
         }
     }
     if (K > 1) {
@@ -277,13 +292,13 @@ __device__ __forceinline__ void march_step(March<ST, K>& S, double (*xch)[March<
         for (int s = 1; s < K; ++s) {
 #pragma unroll
             for (int c = 0; c < W; ++c) {
-                double val;
+                T val;
                 if (c == R) {
                     val = S.own[s];
                 } else {
-                    const double e = xch[s - 1][J][S.xsrc[c]];
+                    const T e = xch[s - 1][J][S.xsrc[c]];
                     if (EDGE)
-                        val = S.xsgn[c] == 0 ? 0.0 : (S.xsgn[c] < 0 ? -e : e);
+                        val = S.xsgn[c] == 0 ? T(0) : (S.xsgn[c] < 0 ? -e : e);
                     else
                         val = e;
                 }
@@ -294,39 +309,38 @@ __device__ __forceinline__ void march_step(March<ST, K>& S, double (*xch)[March<
     }
 }
 
-template <int ST, int K, bool NORM, bool EDGE>
-__device__ __forceinline__ void march(March<ST, K>& S, double (*xch)[March<ST, K>::W][256],
-                                      const double* __restrict__ uin, double* __restrict__ uout,
-                                      const double* __restrict__ g, const double (&om)[K], int ybase, int steps,
-                                      int x, int xg, bool out_col, int Y0, int Y1, int nx, int ny, int pitch,
-                                      double& acc) {
-    constexpr int W = March<ST, K>::W;
+template <typename T, int ST, int K, bool NORM, bool EDGE>
+__device__ __forceinline__ void march(March<T, ST, K>& S, T (*xch)[March<T, ST, K>::W][256],
+                                      const T* __restrict__ uin, T* __restrict__ uout, const T* __restrict__ g,
+                                      const T (&om)[K], int ybase, int steps, int x, int xg, bool out_col, int Y0,
+                                      int Y1, int nx, int ny, int pitch, double& acc) {
+    constexpr int W = March<T, ST, K>::W;
     for (int t = 0; t < steps; t += W) {
-        march_step<ST, K, NORM, EDGE, 0>(S, xch, uin, uout, g, om, t, ybase, x, xg, out_col, Y0, Y1, nx, ny,
-                                         pitch, acc);
-        march_step<ST, K, NORM, EDGE, 1>(S, xch, uin, uout, g, om, t + 1, ybase, x, xg, out_col, Y0, Y1, nx, ny,
-                                         pitch, acc);
-        march_step<ST, K, NORM, EDGE, 2>(S, xch, uin, uout, g, om, t + 2, ybase, x, xg, out_col, Y0, Y1, nx, ny,
-                                         pitch, acc);
+        march_step<T, ST, K, NORM, EDGE, 0>(S, xch, uin, uout, g, om, t, ybase, x, xg, out_col, Y0, Y1, nx, ny,
+                                            pitch, acc);
+        march_step<T, ST, K, NORM, EDGE, 1>(S, xch, uin, uout, g, om, t + 1, ybase, x, xg, out_col, Y0, Y1, nx,
+                                            ny, pitch, acc);
+        march_step<T, ST, K, NORM, EDGE, 2>(S, xch, uin, uout, g, om, t + 2, ybase, x, xg, out_col, Y0, Y1, nx,
+                                            ny, pitch, acc);
         if constexpr (W == 5) {
-            march_step<ST, K, NORM, EDGE, 3>(S, xch, uin, uout, g, om, t + 3, ybase, x, xg, out_col, Y0, Y1, nx,
-                                             ny, pitch, acc);
-            march_step<ST, K, NORM, EDGE, 4>(S, xch, uin, uout, g, om, t + 4, ybase, x, xg, out_col, Y0, Y1, nx,
-                                             ny, pitch, acc);
+            march_step<T, ST, K, NORM, EDGE, 3>(S, xch, uin, uout, g, om, t + 3, ybase, x, xg, out_col, Y0, Y1,
+                                                nx, ny, pitch, acc);
+            march_step<T, ST, K, NORM, EDGE, 4>(S, xch, uin, uout, g, om, t + 4, ybase, x, xg, out_col, Y0, Y1,
+                                                nx, ny, pitch, acc);
         }
     }
 }
 
-template <int ST, int K, bool NORM>
-__global__ __launch_bounds__(256) void sweepk_kernel(
-    const double* __restrict__ uin, double* __restrict__ uout, const double* __restrict__ g,
-    const double* __restrict__ w, int widx, int nx, int ny, int pitch, int strips_x, int rows,
-    double* __restrict__ part) {
-    using MS = March<ST, K>;
+template <typename T, int ST, int K, bool NORM>
+__global__ __launch_bounds__(256) void sweepk_kernel(const T* __restrict__ uin, T* __restrict__ uout,
+                                                     const T* __restrict__ g, const T* __restrict__ w, int widx,
+                                                     int nx, int ny, int pitch, int strips_x, int rows,
+                                                     double* __restrict__ part) {
+    using MS = March<T, ST, K>;
     constexpr int R = MS::R;
     constexpr int W = MS::W;
     constexpr int WOUT = MS::WOUT;
-    __shared__ double xch[K > 1 ? K - 1 : 1][W][256];
+    __shared__ T xch[K > 1 ? K - 1 : 1][W][256];
 
     const int tid = threadIdx.x;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -343,7 +357,7 @@ __global__ __launch_bounds__(256) void sweepk_kernel(
     MS S;
 #pragma unroll
     for (int c = 0; c < W; ++c) {
-        S.lcol[c] = min(max(x - R + c, -1), nx + 2) + kXOff;
+        S.lcol[c] = min(max(x - R + c, -1), nx + 2) + xoff_of(sizeof(T));
         const int dx = c - R, col = x + dx;
         int idx = tid + dx, sg = 1;
         if (col == 0 || col == nx + 1) sg = 0;
@@ -352,46 +366,118 @@ __global__ __launch_bounds__(256) void sweepk_kernel(
         S.xsrc[c] = min(max(idx, 0), 255);
         S.xsgn[c] = sg;
     }
-    double om[K];
+    T om[K];
 #pragma unroll
     for (int s = 0; s < K; ++s) om[s] = w[widx + s];
 #pragma unroll
     for (int s = 0; s < K; ++s) {
 #pragma unroll
         for (int r = 0; r < W; ++r) {
-            S.gw[s][r] = 0.0;
+            S.gw[s][r] = T(0);
 #pragma unroll
-            for (int c = 0; c < W; ++c) S.win[s][r][c] = 0.0;
+            for (int c = 0; c < W; ++c) S.win[s][r][c] = T(0);
         }
     }
     const int ybase = Y0 - K * R;   // level-0 row entering at step 0
     {
         const int yr = min(max(ybase, -1), ny + 2);
-        const double* rowp = uin + (size_t)(yr + 1) * (size_t)pitch;
+        const T* rowp = uin + (size_t)(yr + 1) * (size_t)pitch;
 #pragma unroll
         for (int c = 0; c < W; ++c) S.pre[c] = rowp[S.lcol[c]];
-        S.pg = __builtin_nontemporal_load(g + at(pitch, xg, yr));
+        S.pg = __builtin_nontemporal_load(g + at<T>(pitch, xg, yr));
     }
     double acc = 0.0;
     const int steps = (Y1 - Y0) + 2 * K * R + K - 1;
     if (edge)
-        march<ST, K, NORM, true>(S, xch, uin, uout, g, om, ybase, steps, x, xg, out_col, Y0, Y1, nx, ny, pitch,
-                                 acc);
+        march<T, ST, K, NORM, true>(S, xch, uin, uout, g, om, ybase, steps, x, xg, out_col, Y0, Y1, nx, ny, pitch,
+                                    acc);
     else
-        march<ST, K, NORM, false>(S, xch, uin, uout, g, om, ybase, steps, x, xg, out_col, Y0, Y1, nx, ny, pitch,
-                                  acc);
+        march<T, ST, K, NORM, false>(S, xch, uin, uout, g, om, ybase, steps, x, xg, out_col, Y0, Y1, nx, ny, pitch,
+                                     acc);
     if (NORM) {
         const double tot = block_sum(acc);
         if (threadIdx.x == 0) part[tile] = tot;
     }
 }
 
+// ------------------------------------------------------------ iterative refinement
+// Residual of the FP64 iterate for the FP32 inner solve: r = g - D^{-1}A u in
+// FP64 (same expression as the sweep), rounded to FP32 into r32; the FP32
+// correction d32 is reset to zero (with its reflected ring for 17 points);
+// per-tile partial sums of r^2 in FP64.
+
+template <int ST>
+__global__ __launch_bounds__(256) void ir_residual_kernel(const double* __restrict__ u,
+                                                          const double* __restrict__ g, float* __restrict__ r32,
+                                                          float* __restrict__ d32, int nx, int ny, int pitch,
+                                                          int pitch32, int tiles_x, int rows,
+                                                          double* __restrict__ part) {
+    constexpr int R = Stencil<ST>::R;
+    constexpr int W = 2 * R + 1;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tx = tile % tiles_x, ty = tile / tiles_x;
+    const int x = tx * (int)blockDim.x + (int)threadIdx.x + 1;
+    const bool active = x <= nx;
+    const int xl = active ? x : nx;
+    const int y0 = ty * rows + 1;
+    const int y1 = min(y0 + rows, ny + 1);
+    double v[W][W];
+#pragma unroll
+    for (int r = 1; r < W; ++r) {
+        const double* p = u + at<double>(pitch, xl - R, y0 - R + r - 1);
+#pragma unroll
+        for (int c = 0; c < W; ++c) v[r][c] = p[c];
+    }
+    double acc = 0.0;
+    for (int y = y0; y < y1; ++y) {
+#pragma unroll
+        for (int r = 0; r < W - 1; ++r)
+#pragma unroll
+            for (int c = 0; c < W; ++c) v[r][c] = v[r + 1][c];
+        const double* p = u + at<double>(pitch, xl - R, y + R);
+#pragma unroll
+        for (int c = 0; c < W; ++c) v[W - 1][c] = p[c];
+        const double gv = g[at<double>(pitch, xl, y)];
+        const double res = (gv + neighbour_sum<double, ST>(v)) - v[R][R];
+        acc = fmat<double>(res, res, acc);
+        if (active) {
+            __builtin_nontemporal_store((float)res, r32 + at<float>(pitch32, x, y));
+            store_update<float, ST>(d32, pitch32, nx, ny, x, y, 0.0f);
+        }
+    }
+    if (!active) acc = 0.0;
+    const double tot = block_sum(acc);
+    if (threadIdx.x == 0) part[tile] = tot;
+}
+
+// u += d over the whole padded frame (rows and columns -1 .. n+2): the
+// Dirichlet ring of d is zero and its outer ring holds the reflection of its
+// interior, so u keeps both properties exactly.
+__global__ __launch_bounds__(256) void ir_correct_kernel(double* __restrict__ u, const float* __restrict__ d,
+                                                         int nx, int ny, int pitch, int pitch32, int bx) {
+    const int x = (int)(blockIdx.x % bx) * 256 + (int)threadIdx.x - 1;
+    const int y = (int)(blockIdx.x / bx) - 1;
+    if (x > nx + 2 || y > ny + 2) return;
+    double* p = u + at<double>(pitch, x, y);
+    *p = *p + (double)d[at<float>(pitch32, x, y)];
+}
+
+// dst = (Tout) src over the whole padded frame.
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(256) void convert_kernel(const Tin* __restrict__ src, Tout* __restrict__ dst, int nx,
+                                                      int ny, int pitch_in, int pitch_out, int bx) {
+    const int x = (int)(blockIdx.x % bx) * 256 + (int)threadIdx.x - 1;
+    const int y = (int)(blockIdx.x / bx) - 1;
+    if (x > nx + 2 || y > ny + 2) return;
+    dst[at<Tout>(pitch_out, x, y)] = (Tout)src[at<Tin>(pitch_in, x, y)];
+}
+
 // ------------------------------------------------------------ stage in / out
 
-__global__ __launch_bounds__(256) void stage_in_kernel(
-    const double* __restrict__ f, const double* __restrict__ u, double scale, double* __restrict__ A,
-    double* __restrict__ B, double* __restrict__ G, int nx, int ny, int pitch, int tiles_x, int rows,
-    double* __restrict__ part) {
+__global__ __launch_bounds__(256) void stage_in_kernel(const double* __restrict__ f, const double* __restrict__ u,
+                                                       double scale, double* __restrict__ A, double* __restrict__ B,
+                                                       double* __restrict__ G, int nx, int ny, int pitch,
+                                                       int tiles_x, int rows, double* __restrict__ part) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int x = tx * (int)blockDim.x + (int)threadIdx.x + 1;
@@ -401,13 +487,13 @@ __global__ __launch_bounds__(256) void stage_in_kernel(
     if (x <= nx) {
         for (int y = y0; y < y1; ++y) {
             const size_t src = (size_t)(y - 1) * (size_t)nx + (size_t)(x - 1);
-            const size_t dst = at(pitch, x, y);
+            const size_t dst = at<double>(pitch, x, y);
             const double uv = u[src];
             const double gv = scale * f[src];
             A[dst] = uv;
             B[dst] = uv;
             G[dst] = gv;
-            acc = fma(gv, gv, acc);
+            acc = fmat<double>(gv, gv, acc);
         }
     }
     const double tot = block_sum(acc);
@@ -416,8 +502,8 @@ __global__ __launch_bounds__(256) void stage_in_kernel(
 
 // Ring values: index k enumerates the 2-wide frame around the interior.
 __global__ __launch_bounds__(256) void ring_kernel(const double* __restrict__ u, double* __restrict__ A,
-                                                   double* __restrict__ B, double* __restrict__ G,
-                                                   int nx, int ny, int pitch) {
+                                                   double* __restrict__ B, double* __restrict__ G, int nx, int ny,
+                                                   int pitch) {
     const int W = nx + 4;                 // stored columns -1 .. nx+2
     const int n_rows = 4 * W;             // rows -1, 0, ny+1, ny+2
     const int n_cols = 4 * ny;            // columns -1, 0, nx+1, nx+2 for rows 1..ny
@@ -444,7 +530,7 @@ __global__ __launch_bounds__(256) void ring_kernel(const double* __restrict__ u,
     double val = 0.0;
     if (xs >= 1 && xs <= nx && ys >= 1 && ys <= ny)
         val = sgn * u[(size_t)(ys - 1) * (size_t)nx + (size_t)(xs - 1)];
-    const size_t d = at(pitch, x, y);
+    const size_t d = at<double>(pitch, x, y);
     A[d] = val;
     B[d] = val;
     G[d] = 0.0;
@@ -457,13 +543,12 @@ __global__ __launch_bounds__(256) void stage_out_kernel(const double* __restrict
     const int x = (int)(blockIdx.x % bx) * 256 + (int)threadIdx.x + 1;
     const int y = (int)(blockIdx.x / bx) + 1;
     if (x > nx || y > ny) return;
-    u[(size_t)(y - 1) * (size_t)nx + (size_t)(x - 1)] = A[at(pitch, x, y)];
+    u[(size_t)(y - 1) * (size_t)nx + (size_t)(x - 1)] = A[at<double>(pitch, x, y)];
 }
 
 // ------------------------------------------------------------ reduction / apply
 
-__global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ part, int n,
-                                                     double* __restrict__ out) {
+__global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ part, int n, double* __restrict__ out) {
     double acc = 0.0;
     for (int k = threadIdx.x; k < n; k += blockDim.x) acc += part[k];
     const double tot = block_sum(acc);
@@ -472,8 +557,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ 
 
 template <int ST>
 __global__ __launch_bounds__(256) void apply_kernel(const double* __restrict__ A, double dscale,
-                                                    double* __restrict__ au, int nx, int ny, int pitch,
-                                                    int bx) {
+                                                    double* __restrict__ au, int nx, int ny, int pitch, int bx) {
     constexpr int R = Stencil<ST>::R;
     constexpr int W = 2 * R + 1;
     const int x = (int)(blockIdx.x % bx) * 256 + (int)threadIdx.x + 1;
@@ -483,16 +567,33 @@ __global__ __launch_bounds__(256) void apply_kernel(const double* __restrict__ A
 #pragma unroll
     for (int r = 0; r < W; ++r)
 #pragma unroll
-        for (int c = 0; c < W; ++c) v[r][c] = A[at(pitch, x - R + c, y - R + r)];
-    au[(size_t)(y - 1) * (size_t)nx + (size_t)(x - 1)] = dscale * (v[R][R] - neighbour_sum<ST>(v));
+        for (int c = 0; c < W; ++c) v[r][c] = A[at<double>(pitch, x - R + c, y - R + r)];
+    au[(size_t)(y - 1) * (size_t)nx + (size_t)(x - 1)] = dscale * (v[R][R] - neighbour_sum<double, ST>(v));
 }
 
-template <int ST, bool WRITE, bool NORM>
-hipError_t launch_tile(const Layout& L, const Tiles& T, const double* uin, double* uout, const double* g,
-                       const double* w, int widx, double* part, hipStream_t s) {
-    hipLaunchKernelGGL((sweep_kernel<ST, WRITE, NORM>), dim3(T.count()), dim3(T.width), 0, s, uin, uout, g, w,
-                       widx, L.nx, L.ny, L.pitch, T.tiles_x, T.rows, part);
+template <typename T, int ST, bool WRITE, bool NORM>
+hipError_t launch_tile(const Layout& L, const Tiles& Tl, const T* uin, T* uout, const T* g, const T* w, int widx,
+                       double* part, hipStream_t s) {
+    hipLaunchKernelGGL((sweep_kernel<T, ST, WRITE, NORM>), dim3(Tl.count()), dim3(Tl.width), 0, s, uin, uout, g, w,
+                       widx, L.nx, L.ny, L.pitch, Tl.tiles_x, Tl.rows, part);
     return hipGetLastError();
+}
+
+template <typename T, int ST, int K>
+hipError_t launch_k(const Layout& L, const Tiles& Tl, const T* uin, T* uout, const T* g, const T* w, int widx,
+                    double* part, hipStream_t s) {
+    if (part)
+        hipLaunchKernelGGL((sweepk_kernel<T, ST, K, true>), dim3(Tl.count()), dim3(256), 0, s, uin, uout, g, w,
+                           widx, L.nx, L.ny, L.pitch, Tl.tiles_x, Tl.rows, part);
+    else
+        hipLaunchKernelGGL((sweepk_kernel<T, ST, K, false>), dim3(Tl.count()), dim3(256), 0, s, uin, uout, g, w,
+                           widx, L.nx, L.ny, L.pitch, Tl.tiles_x, Tl.rows, part);
+    return hipGetLastError();
+}
+
+int frame_blocks(const Layout& L, int* bx) {
+    *bx = (L.nx + 4 + 255) / 256;
+    return *bx * (L.ny + 4);
 }
 
 }  // namespace
@@ -508,8 +609,7 @@ hipError_t launch_stage_in(const Layout& L, const Tiles& T, const double* f, con
 
 hipError_t launch_ring(const Layout& L, const double* u, double* A, double* B, double* G, hipStream_t stream) {
     const int n = 4 * (L.nx + 4) + 4 * L.ny;
-    hipLaunchKernelGGL(ring_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, u, A, B, G, L.nx, L.ny,
-                       L.pitch);
+    hipLaunchKernelGGL(ring_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, u, A, B, G, L.nx, L.ny, L.pitch);
     return hipGetLastError();
 }
 
@@ -519,49 +619,66 @@ hipError_t launch_stage_out(const Layout& L, const double* A, double* u, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(int stencil, const Layout& L, const Tiles& T, const double* uin, double* uout,
-                        const double* g, const double* w, int widx, double* part, hipStream_t stream) {
+namespace {
+template <typename T>
+hipError_t sweep_dispatch(int stencil, const Layout& L, const Tiles& Tl, const T* uin, T* uout, const T* g,
+                          const T* w, int widx, double* part, hipStream_t stream) {
     const bool norm = part != nullptr;
+    if (norm && sizeof(T) != sizeof(double)) return hipErrorInvalidValue;
     switch (stencil) {
     case 5:
-        return norm ? launch_tile<5, true, true>(L, T, uin, uout, g, w, widx, part, stream)
-                    : launch_tile<5, true, false>(L, T, uin, uout, g, w, widx, part, stream);
+        return norm ? launch_tile<T, 5, true, true>(L, Tl, uin, uout, g, w, widx, part, stream)
+                    : launch_tile<T, 5, true, false>(L, Tl, uin, uout, g, w, widx, part, stream);
     case 9:
-        return norm ? launch_tile<9, true, true>(L, T, uin, uout, g, w, widx, part, stream)
-                    : launch_tile<9, true, false>(L, T, uin, uout, g, w, widx, part, stream);
+        return norm ? launch_tile<T, 9, true, true>(L, Tl, uin, uout, g, w, widx, part, stream)
+                    : launch_tile<T, 9, true, false>(L, Tl, uin, uout, g, w, widx, part, stream);
     case 17:
-        return norm ? launch_tile<17, true, true>(L, T, uin, uout, g, w, widx, part, stream)
-                    : launch_tile<17, true, false>(L, T, uin, uout, g, w, widx, part, stream);
+        return norm ? launch_tile<T, 17, true, true>(L, Tl, uin, uout, g, w, widx, part, stream)
+                    : launch_tile<T, 17, true, false>(L, Tl, uin, uout, g, w, widx, part, stream);
     default:
         return hipErrorInvalidValue;
     }
 }
-
-namespace {
-template <int ST, int K>
-hipError_t launch_k(const Layout& L, const Tiles& T, const double* uin, double* uout, const double* g,
-                    const double* w, int widx, double* part, hipStream_t s) {
-    if (part)
-        hipLaunchKernelGGL((sweepk_kernel<ST, K, true>), dim3(T.count()), dim3(256), 0, s, uin, uout, g, w, widx,
-                           L.nx, L.ny, L.pitch, T.tiles_x, T.rows, part);
-    else
-        hipLaunchKernelGGL((sweepk_kernel<ST, K, false>), dim3(T.count()), dim3(256), 0, s, uin, uout, g, w, widx,
-                           L.nx, L.ny, L.pitch, T.tiles_x, T.rows, part);
-    return hipGetLastError();
-}
 }  // namespace
 
-bool sweepk_supported(int stencil, int K) {
+hipError_t launch_sweep(int stencil, const Layout& L, const Tiles& Tl, const double* uin, double* uout,
+                        const double* g, const double* w, int widx, double* part, hipStream_t stream) {
+    return sweep_dispatch<double>(stencil, L, Tl, uin, uout, g, w, widx, part, stream);
+}
+
+hipError_t launch_sweep(int stencil, const Layout& L, const Tiles& Tl, const float* uin, float* uout,
+                        const float* g, const float* w, int widx, double* part, hipStream_t stream) {
+    return sweep_dispatch<float>(stencil, L, Tl, uin, uout, g, w, widx, part, stream);
+}
+
+bool sweepk_supported(int stencil, int K, int elem_bytes) {
+    if (elem_bytes == 4) {
+        if (stencil == 17) return K == 2 || K == 3 || K == 4;
+        return K == 2 || K == 4 || K == 8;
+    }
     if (stencil == 17) return K == 2 || K == 3 || K == 4;
     return K == 2 || K == 3 || K == 4 || K == 6 || K == 8;
 }
 
-hipError_t launch_sweepk(int stencil, int K, const Layout& L, const Tiles& T, const double* uin, double* uout,
-                         const double* g, const double* w, int widx, double* part, hipStream_t stream) {
+hipError_t launch_sweepk(int stencil, int K, const Layout& L, const Tiles& Tl, const double* uin,
+                                 double* uout, const double* g, const double* w, int widx, double* part,
+                                 hipStream_t stream) {
 #define CJ_K_CASE(ST, KK) \
-    if (stencil == ST && K == KK) return launch_k<ST, KK>(L, T, uin, uout, g, w, widx, part, stream);
+    if (stencil == ST && K == KK) return launch_k<double, ST, KK>(L, Tl, uin, uout, g, w, widx, part, stream);
     CJ_K_CASE(5, 2) CJ_K_CASE(5, 3) CJ_K_CASE(5, 4) CJ_K_CASE(5, 6) CJ_K_CASE(5, 8)
     CJ_K_CASE(9, 2) CJ_K_CASE(9, 3) CJ_K_CASE(9, 4) CJ_K_CASE(9, 6) CJ_K_CASE(9, 8)
+    CJ_K_CASE(17, 2) CJ_K_CASE(17, 3) CJ_K_CASE(17, 4)
+#undef CJ_K_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweepk(int stencil, int K, const Layout& L, const Tiles& Tl, const float* uin, float* uout,
+                                const float* g, const float* w, int widx, double* part, hipStream_t stream) {
+    if (part) return hipErrorInvalidValue;
+#define CJ_K_CASE(ST, KK) \
+    if (stencil == ST && K == KK) return launch_k<float, ST, KK>(L, Tl, uin, uout, g, w, widx, nullptr, stream);
+    CJ_K_CASE(5, 2) CJ_K_CASE(5, 4) CJ_K_CASE(5, 8)
+    CJ_K_CASE(9, 2) CJ_K_CASE(9, 4) CJ_K_CASE(9, 8)
     CJ_K_CASE(17, 2) CJ_K_CASE(17, 3) CJ_K_CASE(17, 4)
 #undef CJ_K_CASE
     return hipErrorInvalidValue;
@@ -570,11 +687,52 @@ hipError_t launch_sweepk(int stencil, int K, const Layout& L, const Tiles& T, co
 hipError_t launch_residual(int stencil, const Layout& L, const Tiles& T, const double* u, const double* g,
                            double* part, hipStream_t stream) {
     switch (stencil) {
-    case 5: return launch_tile<5, false, true>(L, T, u, nullptr, g, nullptr, 0, part, stream);
-    case 9: return launch_tile<9, false, true>(L, T, u, nullptr, g, nullptr, 0, part, stream);
-    case 17: return launch_tile<17, false, true>(L, T, u, nullptr, g, nullptr, 0, part, stream);
+    case 5: return launch_tile<double, 5, false, true>(L, T, u, nullptr, g, nullptr, 0, part, stream);
+    case 9: return launch_tile<double, 9, false, true>(L, T, u, nullptr, g, nullptr, 0, part, stream);
+    case 17: return launch_tile<double, 17, false, true>(L, T, u, nullptr, g, nullptr, 0, part, stream);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_ir_residual(int stencil, const Layout& L, const Layout& L32, const Tiles& T, const double* u,
+                              const double* g, float* r32, float* d32, double* part, hipStream_t stream) {
+    const dim3 grid(T.count()), block(T.width);
+#define CJ_IR_CASE(ST)                                                                                           \
+    case ST:                                                                                                     \
+        hipLaunchKernelGGL(ir_residual_kernel<ST>, grid, block, 0, stream, u, g, r32, d32, L.nx, L.ny, L.pitch, \
+                           L32.pitch, T.tiles_x, T.rows, part);                                                  \
+        break;
+    switch (stencil) {
+        CJ_IR_CASE(5)
+        CJ_IR_CASE(9)
+        CJ_IR_CASE(17)
+    default: return hipErrorInvalidValue;
+    }
+#undef CJ_IR_CASE
+    return hipGetLastError();
+}
+
+hipError_t launch_ir_correct(const Layout& L, const Layout& L32, double* u, const float* d, hipStream_t stream) {
+    int bx = 0;
+    const int nb = frame_blocks(L, &bx);
+    hipLaunchKernelGGL(ir_correct_kernel, dim3(nb), dim3(256), 0, stream, u, d, L.nx, L.ny, L.pitch, L32.pitch, bx);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_f32(const Layout& L, const Layout& L32, const double* src, float* dst, hipStream_t stream) {
+    int bx = 0;
+    const int nb = frame_blocks(L, &bx);
+    hipLaunchKernelGGL((convert_kernel<double, float>), dim3(nb), dim3(256), 0, stream, src, dst, L.nx, L.ny,
+                       L.pitch, L32.pitch, bx);
+    return hipGetLastError();
+}
+
+hipError_t launch_from_f32(const Layout& L, const Layout& L32, const float* src, double* dst, hipStream_t stream) {
+    int bx = 0;
+    const int nb = frame_blocks(L, &bx);
+    hipLaunchKernelGGL((convert_kernel<float, double>), dim3(nb), dim3(256), 0, stream, src, dst, L.nx, L.ny,
+                       L32.pitch, L.pitch, bx);
+    return hipGetLastError();
 }
 
 hipError_t launch_reduce(const double* part, int n, double* out, hipStream_t stream) {
@@ -597,13 +755,15 @@ hipError_t launch_apply(int stencil, const Layout& L, const double* A, double ds
     return hipGetLastError();
 }
 
-Layout make_layout(int nx, int ny) {
+Layout make_layout(int nx, int ny, int elem_bytes) {
     Layout L;
     L.nx = nx;
     L.ny = ny;
-    int pitch = nx + kXOff + 3;             // columns up to x = nx + 2
-    pitch = (pitch + 15) & ~15;             // 128-byte rows
-    if ((pitch & 511) == 0) pitch += 16;    // avoid 4 KB-multiple row strides
+    L.elem_bytes = elem_bytes;
+    const int line = 128 / elem_bytes;                // elements per 128-byte line
+    int pitch = nx + xoff_of(elem_bytes) + 3;         // columns up to x = nx + 2
+    pitch = (pitch + line - 1) / line * line;         // 128-byte rows
+    if (((long long)pitch * elem_bytes) % 4096 == 0) pitch += line;   // avoid 4 KB-multiple row strides
     L.pitch = pitch;
     L.elems = (size_t)(ny + 4) * (size_t)pitch;
     return L;

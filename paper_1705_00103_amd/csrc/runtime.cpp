@@ -3,17 +3,25 @@
 // A plan holds the schedule (host, FP64) and, after the first device call, a
 // device workspace: two padded iterates A and B (ping-pong), the padded
 // scaled right-hand side G = D^{-1} f, the weights, the per-tile reduction
-// partials and a pinned 8-byte host slot for the cycle-end residual.
+// partials and a pinned 8-byte host slot for the cycle-end residual.  Plans
+// with FP32 sweeps also hold the FP32 residual, two FP32 corrections and the
+// FP32 inner weights.
 //
-// Solve loop: the residual of the iterate reached at a cycle end is produced
-// by the first sweep of the next cycle (the sweep forms r anyway), so the
-// norm costs no extra pass over HBM.  The host waits for that 8-byte value
-// once per cycle and decides; if it stops, the sweep's input (still intact in
-// the other buffer) is the answer.
+// FP64 solve loop: the residual of the iterate reached at a cycle end is
+// produced by the first launch of the next cycle (the sweep forms r anyway),
+// so the norm costs no extra pass over HBM.  The host waits for that 8-byte
+// value once per cycle and decides; if it stops, the launch's input (still
+// intact in the other buffer) is the answer.
+//
+// Refinement loop (FP32 sweeps): r = g - D^{-1}A u is formed in FP64 and
+// rounded to FP32; one inner cycle of FP32 weighted sweeps approximately
+// solves D^{-1}A d = r from d = 0; u += d in FP64; repeat until the FP64
+// residual meets tol.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <initializer_list>
@@ -50,16 +58,28 @@ double centre_over_s(int stencil) {
     }
 }
 
+int radius(int stencil) { return stencil == 17 ? 2 : 1; }
+
 }  // namespace
 
 struct cj_plan_s {
-    cj::Schedule s;
+    cj::Schedule s;       // the FP64 schedule (and the kappa bounds)
+    cj::Schedule sin;     // the inner schedule of the FP32 sweeps (refinement plans)
+    // FP32 weights of the inner cycles of length sin.M, sin.M / 2, ..., 1 (the
+    // refinement halves its inner cycle when an outer step contracts poorly),
+    // concatenated; the cycle of length m starts at w32_offset(m).
+    std::vector<float> w32_all;
+    size_t w32_offset(int m) const { return 2 * (size_t)sin.M - 2 * (size_t)m; }
     cj_options opt;
+    int precision = CJ_PRECISION_F64;
     int max_cycles = 0;
-    cj::Layout L;
+    cj::Layout L;         // FP64 arrays
+    cj::Layout L32;       // FP32 arrays (refinement plans)
     cj::Tiles T;          // single-sweep, stage-in and residual kernels
-    cj::Tiles TK;         // temporally blocked kernel (K > 1)
-    int K = 1;            // sweeps per launch
+    cj::Tiles TK;         // temporally blocked kernel, FP64 (K > 1)
+    cj::Tiles TK32;       // temporally blocked kernel, FP32 (K32 > 1)
+    int K = 1;            // FP64 sweeps per launch
+    int K32 = 1;          // FP32 sweeps per launch
     double D = 0.0;       // diagonal of A: |c_centre| / (s h^2)
     // device state
     int device = -1;
@@ -70,12 +90,23 @@ struct cj_plan_s {
     double* part = nullptr;
     double* scalar = nullptr;
     double* host_slot = nullptr;   // pinned
+    float* R32 = nullptr;
+    float* D1 = nullptr;
+    float* D2 = nullptr;
+    float* W32 = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};   // bracket the plain sweeps of a cycle
+    bool mixed() const { return precision == CJ_PRECISION_F32_REFINE; }
     size_t workspace_bytes() const {
-        return 3 * L.elems * sizeof(double) + (size_t)s.M * sizeof(double) +
-               ((size_t)n_partials() + 64) * sizeof(double);
+        size_t b = 3 * L.elems * sizeof(double) + (size_t)s.M * sizeof(double) +
+                   ((size_t)n_partials() + 64) * sizeof(double);
+        if (mixed()) b += 3 * L32.elems * sizeof(float) + w32_all.size() * sizeof(float);
+        return b;
     }
-    int n_partials() const { return T.count() > TK.count() ? T.count() : TK.count(); }
+    int n_partials() const {
+        int n = T.count();
+        if (TK.count() > n) n = TK.count();
+        return n;
+    }
 };
 
 namespace {
@@ -85,7 +116,8 @@ void release(cj_plan_s* p) {
         int cur = -1;
         (void)hipGetDevice(&cur);
         (void)hipSetDevice(p->device);
-        for (double* d : {p->A, p->B, p->G, p->W, p->part, p->scalar})
+        for (void* d : {(void*)p->A, (void*)p->B, (void*)p->G, (void*)p->W, (void*)p->part, (void*)p->scalar,
+                        (void*)p->R32, (void*)p->D1, (void*)p->D2, (void*)p->W32})
             if (d) (void)hipFree(d);
         if (p->host_slot) (void)hipHostFree(p->host_slot);
         for (hipEvent_t& e : p->ev)
@@ -93,6 +125,7 @@ void release(cj_plan_s* p) {
         if (cur >= 0) (void)hipSetDevice(cur);
     }
     p->A = p->B = p->G = p->W = p->part = p->scalar = p->host_slot = nullptr;
+    p->R32 = p->D1 = p->D2 = p->W32 = nullptr;
     p->ev[0] = p->ev[1] = nullptr;
     p->device = -1;
 }
@@ -119,6 +152,13 @@ cj_status ensure_device(cj_plan_s* p, hipStream_t stream) {
     if (e == hipSuccess) e = hipHostMalloc((void**)&p->host_slot, 64 * sizeof(double), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreate(&p->ev[0]);
     if (e == hipSuccess) e = hipEventCreate(&p->ev[1]);
+    if (p->mixed()) {
+        const size_t b32 = p->L32.elems * sizeof(float);
+        if (e == hipSuccess) e = hipMalloc((void**)&p->R32, b32);
+        if (e == hipSuccess) e = hipMalloc((void**)&p->D1, b32);
+        if (e == hipSuccess) e = hipMalloc((void**)&p->D2, b32);
+        if (e == hipSuccess) e = hipMalloc((void**)&p->W32, p->w32_all.size() * sizeof(float));
+    }
     if (e != hipSuccess) {
         release(p);
         (void)hipGetLastError();
@@ -126,6 +166,14 @@ cj_status ensure_device(cj_plan_s* p, hipStream_t stream) {
                     std::string("workspace allocation: ") + hipGetErrorString(e));
     }
     CJ_HIP(hipMemcpyAsync(p->W, p->s.w.data(), (size_t)p->s.M * sizeof(double), hipMemcpyHostToDevice, stream));
+    if (p->mixed()) {
+        // the corrections' Dirichlet rings stay zero for the life of the plan
+        CJ_HIP(hipMemsetAsync(p->D1, 0, p->L32.elems * sizeof(float), stream));
+        CJ_HIP(hipMemsetAsync(p->D2, 0, p->L32.elems * sizeof(float), stream));
+        CJ_HIP(hipMemsetAsync(p->R32, 0, p->L32.elems * sizeof(float), stream));
+        CJ_HIP(hipMemcpyAsync(p->W32, p->w32_all.data(), p->w32_all.size() * sizeof(float), hipMemcpyHostToDevice,
+                              stream));
+    }
     return CJ_OK;
 }
 
@@ -152,27 +200,29 @@ cj_status stage_in(cj_plan_s* p, const double* f, const double* u, hipStream_t s
     return read_sum(p, p->T.count(), stream, g2);
 }
 
-// Enqueues sweeps [first, first + n) of the cyclic schedule, starting from *cur,
+// Enqueues sweeps [first, first + n) of a cyclic schedule of length M with
+// device weights w, on layout L with right-hand side g, starting from *cur,
 // in launches of K sweeps (single sweeps where a launch would run past the end
-// of the cycle or of the range).  If norm_parts != nullptr the first launch
-// also produces the residual partials of its input and *norm_parts receives
-// their count.  *launches counts the launches.
-cj_status enqueue_sweeps(cj_plan_s* p, long long first, long long n, double** cur, double** nxt,
-                         hipStream_t stream, int* norm_parts = nullptr, long long* launches = nullptr) {
-    const long long M = p->s.M;
+// of the cycle or of the range).  If norm_parts != nullptr (FP64 only) the
+// first launch also produces the residual partials of its input and
+// *norm_parts receives their count.  *launches counts the launches.
+template <typename T>
+cj_status enqueue_sweeps(cj_plan_s* p, int M, int K, const cj::Layout& L, const cj::Tiles& TK, const T* g,
+                         const T* w, long long first, long long n, T** cur, T** nxt, hipStream_t stream,
+                         int* norm_parts = nullptr, long long* launches = nullptr) {
     bool norm = norm_parts != nullptr;
     while (n > 0) {
         const int w0 = (int)(first % M);
-        long long k = p->K;
+        long long k = K;
         if (k > n) k = n;
         if (k > M - w0) k = M - w0;
         double* part = norm ? p->part : nullptr;
-        if (k == p->K && p->K > 1) {
-            CJ_HIP(cj::launch_sweepk(p->s.stencil, p->K, p->L, p->TK, *cur, *nxt, p->G, p->W, w0, part, stream));
-            if (norm) *norm_parts = p->TK.count();
+        if (k == K && K > 1) {
+            CJ_HIP(cj::launch_sweepk(p->s.stencil, K, L, TK, *cur, *nxt, g, w, w0, part, stream));
+            if (norm) *norm_parts = TK.count();
         } else {
             k = 1;
-            CJ_HIP(cj::launch_sweep(p->s.stencil, p->L, p->T, *cur, *nxt, p->G, p->W, w0, part, stream));
+            CJ_HIP(cj::launch_sweep(p->s.stencil, L, p->T, *cur, *nxt, g, w, w0, part, stream));
             if (norm) *norm_parts = p->T.count();
         }
         norm = false;
@@ -182,6 +232,143 @@ cj_status enqueue_sweeps(cj_plan_s* p, long long first, long long n, double** cu
         n -= k;
     }
     return CJ_OK;
+}
+
+cj_status enqueue_f64(cj_plan_s* p, long long first, long long n, double** cur, double** nxt, hipStream_t stream,
+                      int* norm_parts = nullptr, long long* launches = nullptr) {
+    return enqueue_sweeps<double>(p, p->s.M, p->K, p->L, p->TK, p->G, p->W, first, n, cur, nxt, stream, norm_parts,
+                                  launches);
+}
+
+// FP32 sweeps of the inner cycle of length m.
+cj_status enqueue_f32(cj_plan_s* p, int m, long long first, long long n, float** cur, float** nxt,
+                      hipStream_t stream, long long* launches = nullptr) {
+    return enqueue_sweeps<float>(p, m, p->K32, p->L32, p->TK32, p->R32, p->W32 + p->w32_offset(m), first, n, cur,
+                                 nxt, stream, nullptr, launches);
+}
+
+// The FP64 CJM loop (see the file comment).  On return *out_buf is the buffer
+// holding the answer.
+cj_status solve_f64(cj_plan_s* p, double gnorm, hipStream_t stream, cj_result* r, double** out_buf) {
+    cj_status st;
+    double* cur = p->A;
+    double* nxt = p->B;
+    const long long M = p->s.M;
+    double prev = 0.0;
+    cj_status outcome = CJ_OK;
+    int c = 0;
+    bool timed = false;   // events ev[0], ev[1] bracket the previous cycle's plain launches
+    long long timed_launches = 0;
+    // the launch that also yields the norm is a single launch (K sweeps, or one
+    // sweep when the cycle is shorter than K), so that its input stays intact
+    const long long k0 = p->K <= M ? p->K : 1;
+    for (;;) {
+        int nparts = 0;
+        if ((st = enqueue_f64(p, 0, k0, &cur, &nxt, stream, &nparts)) != CJ_OK) return st;
+        double r2 = 0.0;
+        if ((st = read_sum(p, nparts, stream, &r2)) != CJ_OK) return st;
+        if (timed) {
+            float ms = 0.0f;
+            CJ_HIP(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
+            r->sweep_seconds += 1e-3 * (double)ms;
+            r->sweep_launches += timed_launches;
+            timed = false;
+        }
+        const double rr = std::sqrt(r2) / gnorm;
+        r->rel_residual = rr;
+        bool stop = true;
+        if (!std::isfinite(rr)) {
+            outcome = fail(CJ_ERR_NONFINITE, "residual is not finite (u has a NaN or Inf)");
+        } else if (rr <= p->s.tol) {
+            outcome = CJ_OK;
+        } else if (c >= 1 && c >= p->s.cycles_pred && rr > 0.5 * prev) {
+            outcome = CJ_STAGNATED;
+            r->floor_estimate = rr < prev ? rr : prev;
+            g_last_error = "residual stagnated above tol (FP64 floor)";
+        } else if (c >= p->max_cycles) {
+            outcome = fail(CJ_ERR_NOT_CONVERGED, "max_cycles reached");
+        } else {
+            stop = false;
+        }
+        if (stop) {
+            std::swap(cur, nxt);   // the answer is the input of the launch just made
+            break;
+        }
+        prev = rr;
+        if (M > k0) {
+            timed_launches = 0;
+            CJ_HIP(hipEventRecord(p->ev[0], stream));
+            if ((st = enqueue_f64(p, k0, M - k0, &cur, &nxt, stream, nullptr, &timed_launches)) != CJ_OK) return st;
+            CJ_HIP(hipEventRecord(p->ev[1], stream));
+            timed = true;
+        }
+        ++c;
+    }
+    r->cycles = c;
+    r->sweeps = (long long)c * M;
+    *out_buf = cur;
+    return outcome;
+}
+
+// The refinement loop (see the file comment).  The answer is always in A.
+// The inner cycle starts at the plan's length and is halved (down to 16)
+// after an outer step that contracts the residual by less than 1/2: FP32
+// rounding, amplified by the growth of the partial products inside long
+// cycles, can spoil a long inner cycle while a shorter one still contracts.
+// Two consecutive outer steps that reduce the residual by less than 10% stop
+// the solve as stagnated.
+cj_status solve_refine(cj_plan_s* p, double gnorm, hipStream_t stream, cj_result* r) {
+    cj_status st;
+    int m = p->sin.M;
+    double prev = 0.0;
+    cj_status outcome = CJ_OK;
+    int k = 0, fails = 0;
+    long long sweeps = 0;
+    for (;;) {
+        CJ_HIP(cj::launch_ir_residual(p->s.stencil, p->L, p->L32, p->T, p->A, p->G, p->R32, p->D1, p->part, stream));
+        double r2 = 0.0;
+        if ((st = read_sum(p, p->T.count(), stream, &r2)) != CJ_OK) return st;
+        if (k > 0) {
+            float ms = 0.0f;
+            CJ_HIP(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
+            r->sweep_seconds += 1e-3 * (double)ms;
+        }
+        const double rr = std::sqrt(r2) / gnorm;
+        r->rel_residual = rr;
+        const double q = k >= 1 ? rr / prev : 0.0;   // contraction of the last outer step
+        fails = (k >= 1 && q > 0.9) ? fails + 1 : 0;
+        bool stop = true;
+        if (!std::isfinite(rr)) {
+            outcome = fail(CJ_ERR_NONFINITE, "residual is not finite (u has a NaN or Inf)");
+        } else if (rr <= p->s.tol) {
+            outcome = CJ_OK;
+        } else if (fails >= 2) {
+            // the FP64 floor, or the limit eps32 * cond(D^{-1}A) of the FP32 inner solve
+            outcome = CJ_STAGNATED;
+            r->floor_estimate = rr < prev ? rr : prev;
+            g_last_error = "refinement stagnated above tol";
+        } else if (k >= p->max_cycles) {
+            outcome = fail(CJ_ERR_NOT_CONVERGED, "max_cycles (outer steps) reached");
+        } else {
+            stop = false;
+        }
+        if (stop) break;
+        if (k >= 1 && q > 0.5 && m > 16) m /= 2;
+        prev = rr;
+        float* cur = p->D1;
+        float* nxt = p->D2;
+        long long launches = 0;
+        CJ_HIP(hipEventRecord(p->ev[0], stream));
+        if ((st = enqueue_f32(p, m, 0, m, &cur, &nxt, stream, &launches)) != CJ_OK) return st;
+        CJ_HIP(hipEventRecord(p->ev[1], stream));
+        r->sweep_launches += launches;
+        sweeps += m;
+        CJ_HIP(cj::launch_ir_correct(p->L, p->L32, p->A, cur, stream));
+        ++k;
+    }
+    r->cycles = k;
+    r->sweeps = sweeps;
+    return outcome;
 }
 
 }  // namespace
@@ -201,27 +388,55 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol, const cj_o
     if (opt) o = *opt;
     for (int r : o.reserved)
         if (r != 0) return fail(CJ_ERR_ARG, "reserved option fields must be zero");
-    if (o.max_cycles < 0 || o.sweeps_per_launch < 0 || o.tile_rows < 0)
+    if (o.max_cycles < 0 || o.sweeps_per_launch < 0 || o.tile_rows < 0 || o.inner_M < 0)
         return fail(CJ_ERR_ARG, "negative option");
-    if (o.sweeps_per_launch > 1 && !cj::sweepk_supported(stencil, o.sweeps_per_launch))
-        return fail(CJ_ERR_ARG, "sweeps_per_launch not available for this stencil "
-                                "(5/9-point: 1, 2, 3, 4, 6, 8; 17-point: 1, 2, 3, 4)");
+    if (o.precision != CJ_PRECISION_F64 && o.precision != CJ_PRECISION_F32_REFINE)
+        return fail(CJ_ERR_ARG, "precision must be CJ_PRECISION_F64 or CJ_PRECISION_F32_REFINE");
+    const bool mixed = o.precision == CJ_PRECISION_F32_REFINE;
+    const int elem = mixed ? 4 : 8;
+    if (o.sweeps_per_launch > 1 && !cj::sweepk_supported(stencil, o.sweeps_per_launch, elem))
+        return fail(CJ_ERR_ARG, "sweeps_per_launch not available for this stencil and precision "
+                                "(FP64: 5/9-point 1, 2, 3, 4, 6, 8, 17-point 1, 2, 3, 4; "
+                                "FP32: 5/9-point 1, 2, 4, 8, 17-point 1, 2, 3, 4)");
+    if (!mixed && o.inner_M != 0) return fail(CJ_ERR_ARG, "inner_M applies to CJ_PRECISION_F32_REFINE plans only");
     cj_plan_s* p = new (std::nothrow) cj_plan_s();
     if (!p) return fail(CJ_ERR_NOMEM, "host allocation");
     std::string err;
-    if (!cj::make_schedule(stencil, nx, ny, tol, o.h, o.M, &p->s, &err)) {
+    if (!cj::make_schedule(stencil, nx, ny, tol, o.h, o.M, &p->s, &err) ||
+        (mixed && !cj::make_schedule(stencil, nx, ny, tol, o.h, o.inner_M > 0 ? o.inner_M : o.M, &p->sin, &err))) {
         delete p;
         return fail(CJ_ERR_ARG, err);
     }
+    if (mixed) {
+        // inner weight table: cycles of length sin.M, sin.M / 2, ..., 1
+        p->w32_all.assign(2 * (size_t)p->sin.M, 0.0f);
+        for (int m = p->sin.M; m >= 1; m /= 2) {
+            cj::Schedule sm;
+            if (!cj::make_schedule(stencil, nx, ny, tol, o.h, m, &sm, &err)) {
+                delete p;
+                return fail(CJ_ERR_ARG, err);
+            }
+            for (int j = 0; j < m; ++j) p->w32_all[p->w32_offset(m) + j] = (float)sm.w[j];
+        }
+    }
     p->opt = o;
-    p->max_cycles = o.max_cycles > 0 ? o.max_cycles : p->s.cycles_pred + 4;
-    p->L = cj::make_layout(nx, ny);
-    const int R = stencil == 17 ? 2 : 1;
-    // default depths from measurements at 8192^2 on MI355X (9-point: K = 8 is 3.2x the
-    // single-sweep rate; 17-point: K = 3, deeper windows exhaust the registers)
-    p->K = o.sweeps_per_launch > 0 ? o.sweeps_per_launch : (stencil == 17 ? 3 : 8);
-    p->T = cj::make_tiles(nx, ny, p->K == 1 ? o.tile_rows : 0);
-    if (p->K > 1) p->TK = cj::make_tiles_k(nx, ny, p->K, R, o.tile_rows);
+    p->precision = o.precision;
+    p->max_cycles = o.max_cycles > 0 ? o.max_cycles : (mixed ? 50 : p->s.cycles_pred + 4);
+    p->L = cj::make_layout(nx, ny, 8);
+    const int R = radius(stencil);
+    // default depths from measurements at 8192^2 on MI355X (9-point FP64: K = 8 is
+    // 3.2x the single-sweep rate; 17-point: K = 3, deeper windows exhaust the registers)
+    if (mixed) {
+        p->L32 = cj::make_layout(nx, ny, 4);
+        p->K = 1;
+        p->K32 = o.sweeps_per_launch > 0 ? o.sweeps_per_launch : (stencil == 17 ? 4 : 8);
+        p->T = cj::make_tiles(nx, ny, p->K32 == 1 ? o.tile_rows : 0);
+        if (p->K32 > 1) p->TK32 = cj::make_tiles_k(nx, ny, p->K32, R, o.tile_rows);
+    } else {
+        p->K = o.sweeps_per_launch > 0 ? o.sweeps_per_launch : (stencil == 17 ? 3 : 8);
+        p->T = cj::make_tiles(nx, ny, p->K == 1 ? o.tile_rows : 0);
+        if (p->K > 1) p->TK = cj::make_tiles_k(nx, ny, p->K, R, o.tile_rows);
+    }
     p->D = centre_over_s(stencil) / (p->s.h * p->s.h);
     *out = p;
     return CJ_OK;
@@ -234,19 +449,21 @@ cj_status cj_plan(int nx, int ny, int stencil, int bc, double tol, cj_plan_t* ou
 cj_status cj_plan_info(cj_plan_t p, double* kmin, double* kmax, int* M, int* cycles_pred,
                        const double** weights_host, size_t* workspace_bytes) {
     if (!p) return fail(CJ_ERR_ARG, "plan is NULL");
-    if (kmin) *kmin = p->s.kmin;
-    if (kmax) *kmax = p->s.kmax;
-    if (M) *M = p->s.M;
-    if (cycles_pred) *cycles_pred = p->s.cycles_pred;
-    if (weights_host) *weights_host = p->s.w.data();
+    const cj::Schedule& s = p->mixed() ? p->sin : p->s;
+    if (kmin) *kmin = s.kmin;
+    if (kmax) *kmax = s.kmax;
+    if (M) *M = s.M;
+    if (cycles_pred) *cycles_pred = s.cycles_pred;
+    if (weights_host) *weights_host = s.w.data();
     if (workspace_bytes) *workspace_bytes = p->workspace_bytes();
     return CJ_OK;
 }
 
 cj_status cj_plan_launch_info(cj_plan_t p, int* sweeps_per_launch, int* tile_rows, int* workgroups) {
     if (!p) return fail(CJ_ERR_ARG, "plan is NULL");
-    const cj::Tiles& T = p->K > 1 ? p->TK : p->T;
-    if (sweeps_per_launch) *sweeps_per_launch = p->K;
+    const int K = p->mixed() ? p->K32 : p->K;
+    const cj::Tiles& T = K > 1 ? (p->mixed() ? p->TK32 : p->TK) : p->T;
+    if (sweeps_per_launch) *sweeps_per_launch = K;
     if (tile_rows) *tile_rows = T.rows;
     if (workgroups) *workgroups = T.count();
     return CJ_OK;
@@ -278,64 +495,14 @@ cj_status cj_solve(cj_plan_t p, const double* f, double* u, void* stream_, cj_re
         return finish(CJ_OK);
     }
     const double gnorm = std::sqrt(g2);
-    double* cur = p->A;
-    double* nxt = p->B;
-    const long long M = p->s.M;
-    double prev = 0.0;
-    cj_status outcome = CJ_OK;
-    int c = 0;
-    bool timed = false;   // events ev[0], ev[1] bracket the previous cycle's plain launches
-    long long timed_launches = 0;
-    // the launch that also yields the norm is a single launch (K sweeps, or one
-    // sweep when the cycle is shorter than K), so that its input stays intact
-    const long long k0 = p->K <= M ? p->K : 1;
-    for (;;) {
-        // first launch of the next cycle, fused with the residual of its input
-        int nparts = 0;
-        if ((st = enqueue_sweeps(p, 0, k0, &cur, &nxt, stream, &nparts)) != CJ_OK) return finish(st);
-        double r2 = 0.0;
-        if ((st = read_sum(p, nparts, stream, &r2)) != CJ_OK) return finish(st);
-        if (timed) {
-            float ms = 0.0f;
-            CJ_HIP(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
-            r.sweep_seconds += 1e-3 * (double)ms;
-            r.sweep_launches += timed_launches;
-            timed = false;
-        }
-        const double rr = std::sqrt(r2) / gnorm;
-        r.rel_residual = rr;
-        bool stop = true;
-        if (!std::isfinite(rr)) {
-            outcome = fail(CJ_ERR_NONFINITE, "residual is not finite (u has a NaN or Inf)");
-        } else if (rr <= p->s.tol) {
-            outcome = CJ_OK;
-        } else if (c >= 1 && c >= p->s.cycles_pred && rr > 0.5 * prev) {
-            outcome = CJ_STAGNATED;
-            r.floor_estimate = rr < prev ? rr : prev;
-            g_last_error = "residual stagnated above tol (FP64 floor)";
-        } else if (c >= p->max_cycles) {
-            outcome = fail(CJ_ERR_NOT_CONVERGED, "max_cycles reached");
-        } else {
-            stop = false;
-        }
-        if (stop) {
-            std::swap(cur, nxt);   // the answer is the input of the launch just made
-            break;
-        }
-        prev = rr;
-        if (M > k0) {
-            timed_launches = 0;
-            CJ_HIP(hipEventRecord(p->ev[0], stream));
-            if ((st = enqueue_sweeps(p, k0, M - k0, &cur, &nxt, stream, nullptr, &timed_launches)) != CJ_OK)
-                return finish(st);
-            CJ_HIP(hipEventRecord(p->ev[1], stream));
-            timed = true;
-        }
-        ++c;
-    }
-    r.cycles = c;
-    r.sweeps = (long long)c * M;
-    hipError_t e = cj::launch_stage_out(p->L, cur, u, stream);
+    double* answer = p->A;
+    cj_status outcome;
+    if (p->mixed())
+        outcome = solve_refine(p, gnorm, stream, &r);
+    else
+        outcome = solve_f64(p, gnorm, stream, &r, &answer);
+    if (outcome == CJ_ERR_HIP) return finish(outcome);
+    hipError_t e = cj::launch_stage_out(p->L, answer, u, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return finish(fail(CJ_ERR_HIP, hipGetErrorString(e)));
     return finish(outcome);
@@ -350,10 +517,20 @@ cj_status cj_sweeps(cj_plan_t p, const double* f, double* u, long long n_sweeps,
     if ((st = ensure_device(p, stream)) != CJ_OK) return st;
     double g2 = 0.0;
     if ((st = stage_in(p, f, u, stream, &g2)) != CJ_OK) return st;
-    double* cur = p->A;
-    double* nxt = p->B;
-    if ((st = enqueue_sweeps(p, 0, n_sweeps, &cur, &nxt, stream)) != CJ_OK) return st;
-    CJ_HIP(cj::launch_stage_out(p->L, cur, u, stream));
+    double* answer = p->A;
+    if (p->mixed()) {
+        // the plan's working precision: u and g rounded to FP32, FP32 sweeps
+        CJ_HIP(cj::launch_to_f32(p->L, p->L32, p->A, p->D1, stream));
+        CJ_HIP(cj::launch_to_f32(p->L, p->L32, p->G, p->R32, stream));
+        float* cur = p->D1;
+        float* nxt = p->D2;
+        if ((st = enqueue_f32(p, p->sin.M, 0, n_sweeps, &cur, &nxt, stream)) != CJ_OK) return st;
+        CJ_HIP(cj::launch_from_f32(p->L, p->L32, cur, p->A, stream));
+    } else {
+        double* nxt = p->B;
+        if ((st = enqueue_f64(p, 0, n_sweeps, &answer, &nxt, stream)) != CJ_OK) return st;
+    }
+    CJ_HIP(cj::launch_stage_out(p->L, answer, u, stream));
     CJ_HIP(hipStreamSynchronize(stream));
     return CJ_OK;
 }
