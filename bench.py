@@ -124,6 +124,96 @@ def cpu_baseline(f, n, stencil, tol, budget_s):
                       "OpenMP over rows), %.1f s" % (k, n, n, stencil, dt)}
 
 
+def run_batch(args):
+    """Many independent problems: shapes log-uniform over [lo, hi] per axis (seeded),
+    9-point stencil, 16-bump right-hand sides, one tolerance; one step = one
+    batched solve of all of them.  Beside it, the same problems solved one after
+    another with the plain FP64 path and with the single-problem FP32 refinement."""
+    import numpy as np
+    import torch
+    from paper_1705_00103_amd import cj, inputs
+
+    seed = 1705 if args.seed is None else args.seed
+    shapes = inputs.log_uniform_shapes(args.batch_n, seed=seed, lo=args.batch_lo, hi=args.batch_hi)
+    st, tol = args.stencil, args.batch_tol
+    fs = [torch.from_numpy(inputs.gaussian_bumps_rhs(nx, ny, seed=seed + 1 + i)).to("cuda")
+          for i, (nx, ny) in enumerate(shapes)]
+    us = [torch.zeros_like(f) for f in fs]
+    points = sum(nx * ny for nx, ny in shapes)
+    b = cj.Batch(shapes, [st] * len(shapes), [tol] * len(shapes))
+
+    def one_step():
+        for u in us:
+            u.zero_()
+        return b.solve(fs, us)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    lat, last = [], None
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        last = one_step()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+    t1 = time.perf_counter()
+    res, stats = last
+    ms_per_step = (t1 - t0) / args.steps * 1e3
+    value = stats["updates"] / (ms_per_step * 1e-3)
+    statuses = {}
+    for r in res:
+        statuses[r["status"]] = statuses.get(r["status"], 0) + 1
+    out_b = [u.clone() for u in us]
+
+    seq = None
+    if not args.no_sequential:
+        seq = {}
+        for name, prec in (("f64", cj.F64), ("f32_refine", cj.F32_REFINE)):
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            upd, worst_rel, stat = 0.0, 0.0, {}
+            for i, (nx, ny) in enumerate(shapes):
+                p = cj.plan(nx, ny, st, tol, precision=prec)
+                u = torch.zeros_like(fs[i])
+                r = cj.solve(p, fs[i], u)
+                upd += float(nx) * ny * r["sweeps"]
+                stat[r["status"]] = stat.get(r["status"], 0) + 1
+                worst_rel = max(worst_rel, float(torch.linalg.norm(u - out_b[i]) / torch.linalg.norm(u)))
+                p.destroy()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - ts
+            seq[name] = {"seconds": dt, "updates": upd, "updates_per_s": upd / dt, "statuses": stat,
+                         "max_rel_l2_vs_batch": worst_rel}
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "cjm-batch%d-%dpt-logU%d-%d-bumps16-tol%g" % (len(shapes), st, args.batch_lo,
+                                                                          args.batch_hi, tol),
+                   "problems": len(shapes), "points": points, "stencil": st, "tol": tol, "shape_seed": seed,
+                   "parallelism": "single-gpu"},
+        "time_to_tol_p50_ms": float(np.percentile([x * 1e3 for x in lat], 50)),
+        "time_to_tol_p99_ms": float(np.percentile([x * 1e3 for x in lat], 99)),
+        "batch_stats": stats,
+        "statuses": statuses,
+        "sequential": seq,
+    }
+    if seq:
+        out["speedup_vs_sequential_f64"] = seq["f64"]["seconds"] / (ms_per_step * 1e-3)
+        out["speedup_vs_sequential_f32_refine"] = seq["f32_refine"]["seconds"] / (ms_per_step * 1e-3)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +232,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run only the short copy + sweep probe used for rocprofv3 counter passes")
+    ap.add_argument("--workload", choices=("single", "batch"), default="single",
+                    help="single: one large solve (default); batch: many uneven problems in shared launches")
+    ap.add_argument("--batch-n", type=int, default=512)
+    ap.add_argument("--batch-lo", type=int, default=64)
+    ap.add_argument("--batch-hi", type=int, default=2048)
+    ap.add_argument("--batch-tol", type=float, default=1e-8)
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="batch workload: skip the sequential single-problem comparison runs")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -156,6 +254,9 @@ def main():
 
     from paper_1705_00103_amd import cj, inputs
 
+    if args.workload == "batch":
+        run_batch(args)
+        return
     n, st, tol = args.n, args.stencil, args.tol
     ny = args.n if args.ny is None else args.ny
     if args.traffic_probe:

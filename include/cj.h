@@ -163,6 +163,49 @@ cj_status cj_residual(cj_plan_t p, const double* f, const double* u, void* strea
 /* au = A u = -Delta_h u (the stencil apply), same layout as u. */
 cj_status cj_apply(cj_plan_t p, const double* u, double* au, void* stream);
 
+/* ------------------------------------------------------------------ batches
+ * Many independent problems of uneven size solved together (FP32 sweeps
+ * inside FP64 refinement, as CJ_PRECISION_F32_REFINE, per problem).  Each
+ * problem has its own schedule from the paper's closed forms for its nx, ny
+ * (§2.1).  One launch runs K sweeps of every active problem (one workgroup
+ * per problem tile); problems whose inner cycle ends are corrected, their
+ * FP64 residuals formed and reduced together, and the host decides for each
+ * as cj_solve does.  Results per problem match cj_solve on a
+ * CJ_PRECISION_F32_REFINE plan of the same problem up to the order of the
+ * residual reductions. */
+typedef struct cj_batch_s* cj_batch_t;
+
+typedef struct {
+    int       supersteps;      /* batched sweep launches per stencil group */
+    long long launches;        /* batched sweep launches in all */
+    long long points;          /* sum of nx*ny */
+    double    updates;         /* sum of nx*ny*sweeps (FP32 grid-point updates) */
+    double    seconds;         /* host wall time of cj_batch_solve */
+    int       reserved[8];
+} cj_batch_stats;
+
+/* n problems; nx, ny, stencil, tol are arrays of length n (read during the
+ * call only).  opt: precision must be CJ_PRECISION_F32_REFINE; M, inner_M and
+ * h must be 0; sweeps_per_launch 0 (automatic: 8, 17-point 4), 2, 4 or 8;
+ * tile_rows and max_cycles (outer steps per problem, 0 = 50) apply to all.
+ * Host only; the device workspace is allocated by the first solve. */
+cj_status cj_batch_create(int n, const int* nx, const int* ny, const int* stencil, const double* tol,
+                          const cj_options* opt, cj_batch_t* out);
+
+/* Problem i's longest inner cycle M, its sweeps per launch, and the batch's
+ * device workspace in bytes.  Any output pointer may be NULL. */
+cj_status cj_batch_info(cj_batch_t b, int i, int* M, int* sweeps_per_launch, size_t* workspace_bytes);
+
+/* Solves all problems: f[i], u[i] are device pointers laid out as in
+ * cj_solve (u[i] in: guess, out: solution).  results (length n) and stats may
+ * be NULL.  Returns CJ_OK if every problem converged, else the status of the
+ * first problem that did not (per-problem statuses are in results).  Runs on
+ * `stream` and returns when done. */
+cj_status cj_batch_solve(cj_batch_t b, const double* const* f, double* const* u, void* stream,
+                         cj_result* results, cj_batch_stats* stats);
+
+void cj_batch_destroy(cj_batch_t b);
+
 /* Frees the plan and its device workspace.  NULL is ignored. */
 void cj_plan_destroy(cj_plan_t p);
 

@@ -22,7 +22,7 @@ ARCH = os.environ.get("CJ_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-I", INCLUDE, "-I", CSRC]
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 HIP_SOURCES = ["kernels.hip"]
-HOST_SOURCES = ["plan.cpp", "runtime.cpp"]
+HOST_SOURCES = ["plan.cpp", "runtime.cpp", "batch.cpp"]
 
 
 def hipcc():
@@ -50,7 +50,10 @@ def build(verbose=False, save_temps=False):
         objs.append(obj)
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        _run([cc, "-c"] + COMMON + [os.path.join(CSRC, src), "-o", obj], verbose)
+        # host-only sources: plain C++ against the HIP runtime headers
+        _run([cc, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include", "-c"] + COMMON
+             + [os.path.join(CSRC, src), "-o", obj],
+             verbose)
         objs.append(obj)
     tmp = LIB + ".tmp%d" % os.getpid()
     _run([cc, "-shared", "--offload-arch=" + ARCH, "-o", tmp] + objs, verbose)

@@ -36,7 +36,8 @@ STATUS_NAMES = {
 
 # Function names declared in include/cj.h (checked against the header by the tests).
 EXPORTS = ("cj_options_init", "cj_plan", "cj_plan_ex", "cj_plan_info", "cj_plan_launch_info", "cj_solve", "cj_sweeps",
-           "cj_residual", "cj_apply", "cj_plan_destroy", "cj_status_string", "cj_last_error")
+           "cj_residual", "cj_apply", "cj_plan_destroy", "cj_status_string", "cj_last_error",
+           "cj_batch_create", "cj_batch_info", "cj_batch_solve", "cj_batch_destroy")
 
 
 class Options(ctypes.Structure):
@@ -57,6 +58,15 @@ class Result(ctypes.Structure):
                     cycles=self.cycles, sweeps=self.sweeps, rel_residual=self.rel_residual,
                     floor_estimate=self.floor_estimate, seconds=self.seconds,
                     sweep_seconds=self.sweep_seconds, sweep_launches=self.sweep_launches)
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("supersteps", ctypes.c_int), ("launches", ctypes.c_longlong), ("points", ctypes.c_longlong),
+                ("updates", ctypes.c_double), ("seconds", ctypes.c_double), ("reserved", ctypes.c_int * 8)]
+
+    def as_dict(self):
+        return dict(supersteps=self.supersteps, launches=self.launches, points=self.points, updates=self.updates,
+                    seconds=self.seconds)
 
 
 class CJError(RuntimeError):
@@ -99,6 +109,15 @@ def lib():
         L.cj_apply.restype = c_int
         L.cj_plan_destroy.argtypes = [vp]
         L.cj_plan_destroy.restype = None
+        L.cj_batch_create.argtypes = [c_int, ip, ip, ip, dp, ctypes.POINTER(Options), ctypes.POINTER(vp)]
+        L.cj_batch_create.restype = c_int
+        L.cj_batch_info.argtypes = [vp, c_int, ip, ip, ctypes.POINTER(ctypes.c_size_t)]
+        L.cj_batch_info.restype = c_int
+        L.cj_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, ctypes.POINTER(Result),
+                                     ctypes.POINTER(BatchStats)]
+        L.cj_batch_solve.restype = c_int
+        L.cj_batch_destroy.argtypes = [vp]
+        L.cj_batch_destroy.restype = None
         L.cj_status_string.argtypes = [c_int]
         L.cj_status_string.restype = ctypes.c_char_p
         L.cj_last_error.argtypes = []
@@ -217,3 +236,66 @@ def residual(p, f, u, stream=None):
 def apply(p, u, au, stream=None):
     """au = A u."""
     _check(lib().cj_apply(p.handle, _grid_ptr(u, p, "u"), _grid_ptr(au, p, "au"), _stream(stream)), "cj_apply")
+
+
+class Batch:
+    """Owns a cj_batch_t: n problems given as lists of (nx, ny), stencils and tolerances."""
+
+    def __init__(self, shapes, stencils, tols, sweeps_per_launch=0, tile_rows=0, max_cycles=0):
+        L = lib()
+        n = len(shapes)
+        if not (len(stencils) == len(tols) == n):
+            raise ValueError("shapes, stencils and tols must have the same length")
+        self.shapes = [(int(a), int(b)) for a, b in shapes]
+        IA = ctypes.c_int * n
+        nx = IA(*[a for a, _ in self.shapes])
+        ny = IA(*[b for _, b in self.shapes])
+        st = IA(*[int(v) for v in stencils])
+        tl = (ctypes.c_double * n)(*[float(v) for v in tols])
+        o = Options()
+        L.cj_options_init(ctypes.byref(o))
+        o.precision = F32_REFINE
+        o.sweeps_per_launch, o.tile_rows, o.max_cycles = sweeps_per_launch, tile_rows, max_cycles
+        h = ctypes.c_void_p()
+        _check(L.cj_batch_create(n, nx, ny, st, tl, ctypes.byref(o), ctypes.byref(h)), "cj_batch_create")
+        self._h = h
+        self.n = n
+
+    def info(self, i):
+        M, k, ws = ctypes.c_int(), ctypes.c_int(), ctypes.c_size_t()
+        _check(lib().cj_batch_info(self._h, i, ctypes.byref(M), ctypes.byref(k), ctypes.byref(ws)), "cj_batch_info")
+        return dict(M=M.value, sweeps_per_launch=k.value, workspace_bytes=ws.value)
+
+    def solve(self, fs, us, stream=None):
+        """Solves every problem in place (us[i]: guess in, solution out).  Returns
+        (list of per-problem result dicts, stats dict)."""
+        import torch
+        if len(fs) != self.n or len(us) != self.n:
+            raise ValueError("need %d f and u tensors" % self.n)
+        VA = ctypes.c_void_p * self.n
+        fp, up = VA(), VA()
+        for i, ((nx, ny), f, u) in enumerate(zip(self.shapes, fs, us)):
+            for name, t in (("f", f), ("u", u)):
+                if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64 \
+                        or not t.is_contiguous() or t.numel() != nx * ny:
+                    raise ValueError("problem %d: %s must be a contiguous float64 GPU tensor of %d elements"
+                                     % (i, name, nx * ny))
+            fp[i] = f.data_ptr()
+            up[i] = u.data_ptr()
+        res = (Result * self.n)()
+        stats = BatchStats()
+        code = lib().cj_batch_solve(self._h, fp, up, _stream(stream), res, ctypes.byref(stats))
+        if code in (CJ_ERR_ARG, CJ_ERR_NOMEM, CJ_ERR_HIP, CJ_ERR_DEVICE):
+            raise CJError(code, "cj_batch_solve", last_error())
+        return [r.as_dict() for r in res], stats.as_dict()
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.cj_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -58,6 +58,34 @@ Tiles make_tiles(int nx, int ny, int rows_request);
 // columns (tiles_x strips) by tiles of `rows` output rows.
 Tiles make_tiles_k(int nx, int ny, int K, int R, int rows_request);
 
+// ---------------------------------------------------------------- batches
+// Device descriptor of one problem of a batch (FP32 inner sweeps inside FP64
+// refinement).  u and g are FP64 padded arrays (layout pitch), r32, d1, d2
+// FP32 padded arrays (pitch32).  Tile geometry: single-sweep tiles of 256
+// columns x rows (tiles_x per row band) for the residual and correction;
+// blocked strips (strips_x) x rows_k for the sweeps.
+struct BatchProblem {
+    double* u;
+    const double* g;
+    float* r32;
+    float* d1;
+    float* d2;
+    const float* w32;      // weights of the current inner cycle
+    int nx, ny, pitch, pitch32;
+    int tiles_x, rows;     // single-sweep geometry
+    int strips_x, rows_k;  // blocked geometry
+    int cycle_start;       // super-step at which the current inner cycle began
+    int dcur;              // buffer (0: d1, 1: d2) holding the finished correction
+    int dnext;             // buffer the next inner cycle starts from (zeroed by the residual)
+    int pad_;
+};
+
+// One work item: a tile of a problem.
+struct BatchItem {
+    int prob;
+    int tile;
+};
+
 // ---------------------------------------------------------------- launchers
 // Every launcher enqueues on `stream` and returns the launch status.
 
@@ -109,6 +137,16 @@ hipError_t launch_from_f32(const Layout& L, const Layout& L32, const float* src,
 // Per-tile partial sums of r^2 of u (read-only).
 hipError_t launch_residual(int stencil, const Layout& L, const Tiles& T, const double* u,
                            const double* g, double* part, hipStream_t stream);
+
+// Batched launches over a work list of n_items (problem, tile) items.
+hipError_t launch_batch_sweepk(int stencil, int K, const BatchProblem* probs, const BatchItem* work, int n_items,
+                               int step, hipStream_t stream);
+hipError_t launch_batch_correct(int stencil, const BatchProblem* probs, const BatchItem* work, int n_items,
+                                hipStream_t stream);
+hipError_t launch_batch_residual(int stencil, const BatchProblem* probs, const BatchItem* work, int n_items,
+                                 double* part, hipStream_t stream);
+// out[s] <- sum of part[seg[s] .. seg[s+1]) for s < n_seg, fixed order.
+hipError_t launch_segmented_reduce(const double* part, const int* seg, int n_seg, double* out, hipStream_t stream);
 
 // out[0] <- sum of part[0 .. n) in a fixed order (one workgroup).
 hipError_t launch_reduce(const double* part, int n, double* out, hipStream_t stream);

@@ -331,11 +331,11 @@ __device__ __forceinline__ void march(March<T, ST, K>& S, T (*xch)[March<T, ST, 
     }
 }
 
+// The blocked sweeps of one tile (strip sx, row tile sy = tile / strips_x).
 template <typename T, int ST, int K, bool NORM>
-__global__ __launch_bounds__(256) void sweepk_kernel(const T* __restrict__ uin, T* __restrict__ uout,
-                                                     const T* __restrict__ g, const T* __restrict__ w, int widx,
-                                                     int nx, int ny, int pitch, int strips_x, int rows,
-                                                     double* __restrict__ part) {
+__device__ __forceinline__ void sweepk_tile(const T* __restrict__ uin, T* __restrict__ uout, const T* __restrict__ g,
+                                            const T* __restrict__ w, int widx, int nx, int ny, int pitch,
+                                            int strips_x, int rows, int tile, double* __restrict__ part) {
     using MS = March<T, ST, K>;
     constexpr int R = MS::R;
     constexpr int W = MS::W;
@@ -343,7 +343,6 @@ __global__ __launch_bounds__(256) void sweepk_kernel(const T* __restrict__ uin, 
     __shared__ T xch[K > 1 ? K - 1 : 1][W][256];
 
     const int tid = threadIdx.x;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int sx = tile % strips_x, sy = tile / strips_x;
     const int X0 = sx * WOUT + 1;
     const int x = X0 - K * R + tid;
@@ -398,6 +397,115 @@ __global__ __launch_bounds__(256) void sweepk_kernel(const T* __restrict__ uin, 
         const double tot = block_sum(acc);
         if (threadIdx.x == 0) part[tile] = tot;
     }
+}
+
+template <typename T, int ST, int K, bool NORM>
+__global__ __launch_bounds__(256) void sweepk_kernel(const T* __restrict__ uin, T* __restrict__ uout,
+                                                     const T* __restrict__ g, const T* __restrict__ w, int widx,
+                                                     int nx, int ny, int pitch, int strips_x, int rows,
+                                                     double* __restrict__ part) {
+    sweepk_tile<T, ST, K, NORM>(uin, uout, g, w, widx, nx, ny, pitch, strips_x, rows,
+                                xcd_tile(blockIdx.x, gridDim.x), part);
+}
+
+// ------------------------------------------------------------ batched problems
+// Many independent problems advance together: one launch runs K FP32 sweeps of
+// every problem on the work list; workgroup b (mapped XCD-contiguously) takes
+// work item b = (problem, tile).  A problem's current inner cycle began at
+// super-step cycle_start; launch j = step - cycle_start of the cycle reads
+// the correction buffer d[j & 1], writes d[(j + 1) & 1] and uses the weights
+// w32[jK .. jK + K - 1].
+
+template <int ST, int K>
+__global__ __launch_bounds__(256) void batch_sweepk_kernel(const BatchProblem* __restrict__ probs,
+                                                           const BatchItem* __restrict__ work, int step) {
+    const BatchItem it = work[xcd_tile(blockIdx.x, gridDim.x)];
+    const BatchProblem& pb = probs[it.prob];
+    const int j = step - pb.cycle_start;
+    const float* uin = (j & 1) ? pb.d2 : pb.d1;
+    float* uout = (j & 1) ? pb.d1 : pb.d2;
+    sweepk_tile<float, ST, K, false>(uin, uout, pb.r32, pb.w32, j * K, pb.nx, pb.ny, pb.pitch32, pb.strips_x,
+                                     pb.rows_k, it.tile, nullptr);
+}
+
+// Cycle end of one problem, per tile of the single-sweep geometry: u += d
+// (interior; the 17-point outer ring follows by reflection, the Dirichlet ring
+// stays zero).
+template <int ST>
+__global__ __launch_bounds__(256) void batch_correct_kernel(const BatchProblem* __restrict__ probs,
+                                                            const BatchItem* __restrict__ work) {
+    const BatchItem it = work[xcd_tile(blockIdx.x, gridDim.x)];
+    const BatchProblem& pb = probs[it.prob];
+    const float* d = pb.dcur ? pb.d2 : pb.d1;
+    const int tx = it.tile % pb.tiles_x, ty = it.tile / pb.tiles_x;
+    const int x = tx * 256 + (int)threadIdx.x + 1;
+    if (x > pb.nx) return;
+    const int y0 = ty * pb.rows + 1;
+    const int y1 = min(y0 + pb.rows, pb.ny + 1);
+    for (int y = y0; y < y1; ++y) {
+        const double un = pb.u[at<double>(pb.pitch, x, y)] + (double)d[at<float>(pb.pitch32, x, y)];
+        store_update<double, ST>(pb.u, pb.pitch, pb.nx, pb.ny, x, y, un);
+    }
+}
+
+// Residual of one problem for its next inner solve, per tile: r32 <- (float)r,
+// the correction buffer d[dnext] <- 0 (with its reflected ring), partial sums
+// of r^2 into part[work index].
+template <int ST>
+__global__ __launch_bounds__(256) void batch_residual_kernel(const BatchProblem* __restrict__ probs,
+                                                             const BatchItem* __restrict__ work,
+                                                             double* __restrict__ part) {
+    constexpr int R = Stencil<ST>::R;
+    constexpr int W = 2 * R + 1;
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
+    const BatchItem it = work[b];
+    const BatchProblem& pb = probs[it.prob];
+    float* dz = pb.dnext ? pb.d2 : pb.d1;
+    const int nx = pb.nx, ny = pb.ny, pitch = pb.pitch, pitch32 = pb.pitch32;
+    const int tx = it.tile % pb.tiles_x, ty = it.tile / pb.tiles_x;
+    const int x = tx * 256 + (int)threadIdx.x + 1;
+    const bool active = x <= nx;
+    const int xl = active ? x : nx;
+    const int y0 = ty * pb.rows + 1;
+    const int y1 = min(y0 + pb.rows, ny + 1);
+    double v[W][W];
+#pragma unroll
+    for (int r = 1; r < W; ++r) {
+        const double* p = pb.u + at<double>(pitch, xl - R, y0 - R + r - 1);
+#pragma unroll
+        for (int c = 0; c < W; ++c) v[r][c] = p[c];
+    }
+    double acc = 0.0;
+    for (int y = y0; y < y1; ++y) {
+#pragma unroll
+        for (int r = 0; r < W - 1; ++r)
+#pragma unroll
+            for (int c = 0; c < W; ++c) v[r][c] = v[r + 1][c];
+        const double* p = pb.u + at<double>(pitch, xl - R, y + R);
+#pragma unroll
+        for (int c = 0; c < W; ++c) v[W - 1][c] = p[c];
+        const double gv = pb.g[at<double>(pitch, xl, y)];
+        const double res = (gv + neighbour_sum<double, ST>(v)) - v[R][R];
+        acc = fmat<double>(res, res, acc);
+        if (active) {
+            __builtin_nontemporal_store((float)res, pb.r32 + at<float>(pitch32, x, y));
+            store_update<float, ST>(dz, pitch32, nx, ny, x, y, 0.0f);
+        }
+    }
+    if (!active) acc = 0.0;
+    const double tot = block_sum(acc);
+    if (threadIdx.x == 0) part[b] = tot;
+}
+
+// out[s] <- sum of part[seg[s] .. seg[s + 1]) in a fixed order; one workgroup per segment.
+__global__ __launch_bounds__(256) void segmented_reduce_kernel(const double* __restrict__ part,
+                                                               const int* __restrict__ seg,
+                                                               double* __restrict__ out) {
+    const int s = blockIdx.x;
+    double acc = 0.0;
+    for (int k = seg[s] + (int)threadIdx.x; k < seg[s + 1]; k += blockDim.x) acc += part[k];
+    const double tot = block_sum(acc);
+    if (threadIdx.x == 0) out[s] = tot;
 }
 
 // ------------------------------------------------------------ iterative refinement
@@ -732,6 +840,58 @@ hipError_t launch_from_f32(const Layout& L, const Layout& L32, const float* src,
     const int nb = frame_blocks(L, &bx);
     hipLaunchKernelGGL((convert_kernel<float, double>), dim3(nb), dim3(256), 0, stream, src, dst, L.nx, L.ny,
                        L32.pitch, L.pitch, bx);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_sweepk(int stencil, int K, const BatchProblem* probs, const BatchItem* work, int n_items,
+                               int step, hipStream_t stream) {
+    if (n_items <= 0) return hipSuccess;
+#define CJ_BK_CASE(ST, KK)                                                                                   \
+    if (stencil == ST && K == KK) {                                                                        \
+        hipLaunchKernelGGL((batch_sweepk_kernel<ST, KK>), dim3(n_items), dim3(256), 0, stream, probs, work, \
+                           step);                                                                          \
+        return hipGetLastError();                                                                          \
+    }
+    CJ_BK_CASE(5, 2) CJ_BK_CASE(5, 4) CJ_BK_CASE(5, 8)
+    CJ_BK_CASE(9, 2) CJ_BK_CASE(9, 4) CJ_BK_CASE(9, 8)
+    CJ_BK_CASE(17, 2) CJ_BK_CASE(17, 3) CJ_BK_CASE(17, 4)
+#undef CJ_BK_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_correct(int stencil, const BatchProblem* probs, const BatchItem* work, int n_items,
+                                hipStream_t stream) {
+    if (n_items <= 0) return hipSuccess;
+    switch (stencil) {
+    case 5: hipLaunchKernelGGL(batch_correct_kernel<5>, dim3(n_items), dim3(256), 0, stream, probs, work); break;
+    case 9: hipLaunchKernelGGL(batch_correct_kernel<9>, dim3(n_items), dim3(256), 0, stream, probs, work); break;
+    case 17: hipLaunchKernelGGL(batch_correct_kernel<17>, dim3(n_items), dim3(256), 0, stream, probs, work); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_residual(int stencil, const BatchProblem* probs, const BatchItem* work, int n_items,
+                                 double* part, hipStream_t stream) {
+    if (n_items <= 0) return hipSuccess;
+    switch (stencil) {
+    case 5:
+        hipLaunchKernelGGL(batch_residual_kernel<5>, dim3(n_items), dim3(256), 0, stream, probs, work, part);
+        break;
+    case 9:
+        hipLaunchKernelGGL(batch_residual_kernel<9>, dim3(n_items), dim3(256), 0, stream, probs, work, part);
+        break;
+    case 17:
+        hipLaunchKernelGGL(batch_residual_kernel<17>, dim3(n_items), dim3(256), 0, stream, probs, work, part);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_segmented_reduce(const double* part, const int* seg, int n_seg, double* out, hipStream_t stream) {
+    if (n_seg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(segmented_reduce_kernel, dim3(n_seg), dim3(256), 0, stream, part, seg, out);
     return hipGetLastError();
 }
 

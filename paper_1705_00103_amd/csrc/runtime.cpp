@@ -587,4 +587,7 @@ const char* cj_status_string(int s) {
 
 const char* cj_last_error(void) { return g_last_error.c_str(); }
 
+// Lets the batch module report through cj_last_error (not part of the public header).
+void cj_internal_set_error(const char* msg) { g_last_error = msg ? msg : ""; }
+
 }  // extern "C"

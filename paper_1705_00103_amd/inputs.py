@@ -63,3 +63,11 @@ def random_field(nx, ny, seed, scale=1.0):
     """Uniform(-scale, scale) values, e.g. a rough initial guess or a rough RHS."""
     rng = np.random.default_rng(seed)
     return rng.uniform(-scale, scale, (ny, nx))
+
+
+def log_uniform_shapes(n, seed, lo=64, hi=2048):
+    """n grid shapes (nx, ny), each drawn independently log-uniform over [lo, hi]
+    (rounded to integers) from default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    a = np.exp(rng.uniform(math.log(lo), math.log(hi), (n, 2)))
+    return [(int(round(x)), int(round(y))) for x, y in a]

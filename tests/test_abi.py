@@ -104,3 +104,26 @@ def test_weights_are_positive_and_span_the_interval():
     assert max(p.weights) < 1.0 / p.kmin * 1.01
     assert len(set(p.weights)) == p.M
     assert math.isclose(sum(1.0 / w for w in p.weights) / p.M, (p.kmax + p.kmin) / 2, rel_tol=1e-12)
+
+
+def test_batch_create_host_side():
+    shapes = [(64, 80), (300, 17), (1, 1), (129, 129)]
+    b = cj.Batch(shapes, [9, 5, 17, 9], [1e-8, 1e-6, 1e-10, 1e-8])
+    for i, (nx, ny) in enumerate(shapes):
+        inf = b.info(i)
+        st = [9, 5, 17, 9][i]
+        p = cj.plan(nx, ny, st, [1e-8, 1e-6, 1e-10, 1e-8][i], precision=cj.F32_REFINE)
+        assert inf["M"] == max(p.M, 16)
+        assert inf["sweeps_per_launch"] == (4 if st == 17 else 8)
+    assert b.info(0)["workspace_bytes"] > 0
+    b.destroy()
+    with pytest.raises(cj.CJError):
+        cj.Batch([(10, 10)], [7], [1e-8])
+    with pytest.raises(cj.CJError):
+        cj.Batch([(10, 10)], [9], [0.0])
+    with pytest.raises(cj.CJError):
+        cj.Batch([(10, 10)], [9], [1e-8], sweeps_per_launch=3)
+    L = cj.lib()
+    assert L.cj_batch_create(0, None, None, None, None, None, ctypes.byref(ctypes.c_void_p())) == cj.CJ_ERR_ARG
+    assert L.cj_batch_solve(None, None, None, None, None, None) == cj.CJ_ERR_ARG
+    L.cj_batch_destroy(None)
