@@ -214,6 +214,107 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def run_serve(args):
+    """Serving: requests arrive as a Poisson process (seeded), sizes log-uniform over
+    [lo, hi] per axis (square and rectangular), stencil 5 or 9 with equal odds,
+    tolerance uniform over {1e-6, 1e-8, 1e-10}.  The server (continuous batching,
+    FP32 sweeps inside FP64 refinement, admission by an HBM budget) is stepped in
+    real time.  The baseline is the same request stream served one request at a
+    time by the plain FP64 solve (FIFO, measured service times)."""
+    import numpy as np
+    import torch
+    from paper_1705_00103_amd import cj, inputs
+
+    seed = 1705 if args.seed is None else args.seed
+    rng = np.random.default_rng(seed)
+    n = args.serve_n
+    gaps = rng.exponential(1.0 / args.serve_rate, n)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    shapes = inputs.log_uniform_shapes(n, seed=seed + 1, lo=args.serve_lo, hi=args.serve_hi)
+    stencils = [int(v) for v in rng.choice([5, 9], n)]
+    tols = [float(v) for v in rng.choice([1e-6, 1e-8, 1e-10], n)]
+    fs = [torch.from_numpy(inputs.gaussian_bumps_rhs(nx, ny, seed=seed + 10 + i)).to("cuda")
+          for i, (nx, ny) in enumerate(shapes)]
+    us = [torch.zeros_like(f) for f in fs]
+    torch.cuda.synchronize()
+
+    srv = cj.Server(hbm_budget_bytes=int(args.serve_budget_gib * (1 << 30)))
+    lat = [None] * n
+    res = [None] * n
+    tickets = {}
+    nxt = 0
+    steps = 0
+    t0 = time.perf_counter()
+    while nxt < n or len(tickets) > 0:
+        now = time.perf_counter() - t0
+        while nxt < n and arrivals[nxt] <= now:
+            nx, ny = shapes[nxt]
+            tickets[srv.submit(nx, ny, stencils[nxt], tols[nxt], fs[nxt], us[nxt])] = nxt
+            nxt += 1
+        if not tickets:
+            time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
+            continue
+        for tk, r in srv.step():
+            i = tickets.pop(tk)
+            res[i] = r
+            lat[i] = (time.perf_counter() - t0) - arrivals[i]
+        steps += 1
+    makespan = time.perf_counter() - t0
+    srv.destroy()
+    updates = sum(float(nx) * ny * r["sweeps"] for (nx, ny), r in zip(shapes, res))
+    statuses = {}
+    for r in res:
+        statuses[r["status"]] = statuses.get(r["status"], 0) + 1
+
+    # baseline: plain FP64 solves one at a time, FIFO over the same arrivals
+    service, upd64, st64, worst = [], 0.0, {}, 0.0
+    for i, (nx, ny) in enumerate(shapes):
+        p = cj.plan(nx, ny, stencils[i], tols[i])
+        u = torch.zeros_like(fs[i])
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        r = cj.solve(p, fs[i], u)
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - ts)
+        upd64 += float(nx) * ny * r["sweeps"]
+        st64[r["status"]] = st64.get(r["status"], 0) + 1
+        worst = max(worst, float(torch.linalg.norm(u - us[i]) / torch.linalg.norm(u)))
+        p.destroy()
+    free_at, lat64 = 0.0, []
+    for a, sv in zip(arrivals, service):
+        start = max(a, free_at)
+        free_at = start + sv
+        lat64.append(free_at - a)
+    out = {
+        "metric": METRIC,
+        "value": updates / makespan,
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": makespan * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "cjm-serve-poisson%g-n%d-logU%d-%d-st5or9-tol1e-6to1e-10" % (
+            args.serve_rate, n, args.serve_lo, args.serve_hi),
+                   "requests": n, "rate_per_s": args.serve_rate, "hbm_budget_gib": args.serve_budget_gib,
+                   "points": int(sum(nx * ny for nx, ny in shapes)), "seed": seed, "parallelism": "single-gpu"},
+        "latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
+        "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "server_steps": steps,
+        "statuses": statuses,
+        "sequential_f64": {"latency_p50_ms": float(np.percentile(lat64, 50) * 1e3),
+                           "latency_p99_ms": float(np.percentile(lat64, 99) * 1e3),
+                           "makespan_s": float(max(a + l for a, l in zip(arrivals, lat64))),
+                           "busy_s": float(sum(service)), "updates_per_s_busy": upd64 / sum(service),
+                           "statuses": st64, "max_rel_l2_vs_served": worst},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,8 +333,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run only the short copy + sweep probe used for rocprofv3 counter passes")
-    ap.add_argument("--workload", choices=("single", "batch"), default="single",
-                    help="single: one large solve (default); batch: many uneven problems in shared launches")
+    ap.add_argument("--workload", choices=("single", "batch", "serve"), default="single",
+                    help="single: one large solve (default); batch: many uneven problems in shared launches; "
+                         "serve: Poisson arrivals into the continuous-batching server")
+    ap.add_argument("--serve-n", type=int, default=160, help="serve: number of requests")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="serve: arrivals per second")
+    ap.add_argument("--serve-lo", type=int, default=64)
+    ap.add_argument("--serve-hi", type=int, default=4096)
+    ap.add_argument("--serve-budget-gib", type=float, default=16.0)
     ap.add_argument("--batch-n", type=int, default=512)
     ap.add_argument("--batch-lo", type=int, default=64)
     ap.add_argument("--batch-hi", type=int, default=2048)
@@ -256,6 +363,9 @@ def main():
 
     if args.workload == "batch":
         run_batch(args)
+        return
+    if args.workload == "serve":
+        run_serve(args)
         return
     n, st, tol = args.n, args.stencil, args.tol
     ny = args.n if args.ny is None else args.ny

@@ -206,6 +206,40 @@ cj_status cj_batch_solve(cj_batch_t b, const double* const* f, double* const* u,
 
 void cj_batch_destroy(cj_batch_t b);
 
+/* ------------------------------------------------------------------ serving
+ * Continuous batching: requests are submitted at any time and join the
+ * running batch as HBM budget frees up; each is admitted when its device
+ * arrays fit in the server's pool, runs in the shared launches of the
+ * batched solver (as described above), and leaves when finished.  A
+ * request's arithmetic does not depend on which other requests share its
+ * launches, so its result is the same alone and in the mix.
+ * The server does work only inside cj_server_step. */
+typedef struct cj_server_s* cj_server_t;
+
+/* opt as for cj_batch_create.  hbm_budget_bytes: the device pool that
+ * admission draws from (allocated at the first step).  stream: all work of
+ * the server runs on it (hipStream_t as void*). */
+cj_status cj_server_create(const cj_options* opt, size_t hbm_budget_bytes, void* stream, cj_server_t* out);
+
+/* Queues a request.  f, u: device arrays as in cj_solve, owned by the caller
+ * and left untouched by the caller until the request is reported done (u is
+ * the initial guess and receives the solution).  *ticket identifies it.
+ * CJ_ERR_NOMEM if the request alone exceeds the HBM budget. */
+cj_status cj_server_submit(cj_server_t s, int nx, int ny, int stencil, double tol, const double* f, double* u,
+                           long long* ticket);
+
+/* Admits what fits, advances every admitted request by one batched launch
+ * (with cycle-end work where due) and reports up to max_done finished
+ * requests (tickets and results; results[].seconds is the time from submit
+ * to completion).  *n_done receives their number. */
+cj_status cj_server_step(cj_server_t s, long long* done_tickets, cj_result* done_results, int max_done,
+                         int* n_done);
+
+/* Requests admitted and not finished, requests waiting, pool bytes in use. */
+cj_status cj_server_stats(cj_server_t s, int* active, int* queued, size_t* bytes_in_use);
+
+void cj_server_destroy(cj_server_t s);
+
 /* Frees the plan and its device workspace.  NULL is ignored. */
 void cj_plan_destroy(cj_plan_t p);
 

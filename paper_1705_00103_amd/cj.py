@@ -37,7 +37,8 @@ STATUS_NAMES = {
 # Function names declared in include/cj.h (checked against the header by the tests).
 EXPORTS = ("cj_options_init", "cj_plan", "cj_plan_ex", "cj_plan_info", "cj_plan_launch_info", "cj_solve", "cj_sweeps",
            "cj_residual", "cj_apply", "cj_plan_destroy", "cj_status_string", "cj_last_error",
-           "cj_batch_create", "cj_batch_info", "cj_batch_solve", "cj_batch_destroy")
+           "cj_batch_create", "cj_batch_info", "cj_batch_solve", "cj_batch_destroy",
+           "cj_server_create", "cj_server_submit", "cj_server_step", "cj_server_stats", "cj_server_destroy")
 
 
 class Options(ctypes.Structure):
@@ -118,6 +119,16 @@ def lib():
         L.cj_batch_solve.restype = c_int
         L.cj_batch_destroy.argtypes = [vp]
         L.cj_batch_destroy.restype = None
+        L.cj_server_create.argtypes = [ctypes.POINTER(Options), ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+        L.cj_server_create.restype = c_int
+        L.cj_server_submit.argtypes = [vp, c_int, c_int, c_int, c_double, vp, vp, ctypes.POINTER(ctypes.c_longlong)]
+        L.cj_server_submit.restype = c_int
+        L.cj_server_step.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(Result), c_int, ip]
+        L.cj_server_step.restype = c_int
+        L.cj_server_stats.argtypes = [vp, ip, ip, ctypes.POINTER(ctypes.c_size_t)]
+        L.cj_server_stats.restype = c_int
+        L.cj_server_destroy.argtypes = [vp]
+        L.cj_server_destroy.restype = None
         L.cj_status_string.argtypes = [c_int]
         L.cj_status_string.restype = ctypes.c_char_p
         L.cj_last_error.argtypes = []
@@ -292,6 +303,64 @@ class Batch:
     def destroy(self):
         if getattr(self, "_h", None) is not None and _lib is not None:
             _lib.cj_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class Server:
+    """Owns a cj_server_t (continuous batching of solve requests)."""
+
+    def __init__(self, hbm_budget_bytes, stream=None, sweeps_per_launch=0, tile_rows=0, max_cycles=0):
+        L = lib()
+        o = Options()
+        L.cj_options_init(ctypes.byref(o))
+        o.precision = F32_REFINE
+        o.sweeps_per_launch, o.tile_rows, o.max_cycles = sweeps_per_launch, tile_rows, max_cycles
+        h = ctypes.c_void_p()
+        _check(L.cj_server_create(ctypes.byref(o), int(hbm_budget_bytes), _stream(stream), ctypes.byref(h)),
+               "cj_server_create")
+        self._h = h
+        self._keep = {}     # ticket -> (f, u) kept alive until done
+
+    def submit(self, nx, ny, stencil, tol, f, u):
+        import torch
+        for name, t in (("f", f), ("u", u)):
+            if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64 \
+                    or not t.is_contiguous() or t.numel() != nx * ny:
+                raise ValueError("%s must be a contiguous float64 GPU tensor of nx*ny elements" % name)
+        tk = ctypes.c_longlong()
+        _check(lib().cj_server_submit(self._h, nx, ny, stencil, tol, ctypes.c_void_p(f.data_ptr()),
+                                      ctypes.c_void_p(u.data_ptr()), ctypes.byref(tk)), "cj_server_submit")
+        self._keep[tk.value] = (f, u)
+        return tk.value
+
+    def step(self, max_done=256):
+        """One server step; returns a list of (ticket, result dict) finished in it."""
+        tks = (ctypes.c_longlong * max_done)()
+        res = (Result * max_done)()
+        nd = ctypes.c_int()
+        code = lib().cj_server_step(self._h, tks, res, max_done, ctypes.byref(nd))
+        out = []
+        for k in range(nd.value):
+            self._keep.pop(tks[k], None)
+            out.append((tks[k], res[k].as_dict()))
+        if code in (CJ_ERR_ARG, CJ_ERR_NOMEM, CJ_ERR_HIP, CJ_ERR_DEVICE):
+            raise CJError(code, "cj_server_step", last_error())
+        return out
+
+    def stats(self):
+        a, q, b = ctypes.c_int(), ctypes.c_int(), ctypes.c_size_t()
+        _check(lib().cj_server_stats(self._h, ctypes.byref(a), ctypes.byref(q), ctypes.byref(b)), "cj_server_stats")
+        return dict(active=a.value, queued=q.value, bytes_in_use=b.value)
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.cj_server_destroy(self._h)
         self._h = None
 
     def __del__(self):

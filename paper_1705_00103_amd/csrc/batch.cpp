@@ -1,18 +1,25 @@
-// Batched solves (C ABI cj_batch_*, declared in include/cj.h): many
-// independent Poisson problems of uneven size, each with its own schedule,
-// advance together in FP32 sweeps inside FP64 refinement.
+// Batched and served solves (C ABI cj_batch_* and cj_server_*, declared in
+// include/cj.h): many independent Poisson problems of uneven size, each with
+// its own schedule, advance together in FP32 sweeps inside FP64 refinement.
 //
-// Super-step loop.  Every super-step is one launch per stencil group that runs
-// K FP32 sweeps of every active problem (one workgroup per (problem, tile)
-// work item).  A problem whose inner cycle ends in that super-step joins the
-// cycle-end set E; for E, two more batched launches add the correction to u
-// (FP64) and form the next FP64 residual (rounded to FP32, plus per-tile
-// partial norms), a segmented reduction gives each problem's residual norm,
-// and one small device-to-host copy brings those norms back.  The host then
-// decides for each problem of E exactly as the single-problem refinement does
-// (converged, stagnated, or the next inner cycle, halved when the last outer
-// step contracted by less than 1/2) and rebuilds the work list when problems
-// leave.  Between cycle ends the host only enqueues launches.
+// Both APIs drive one engine.  Problems live in a device pool (the HBM
+// budget); a problem is admitted when its arrays fit in the pool and leaves
+// when it is finished, freeing its space for the next.
+//
+// Engine step (one "super-step"):
+//   1. admit queued problems that fit: allocate, stage u and g = D^{-1} f in;
+//   2. one launch per stencil group runs K FP32 sweeps of every active problem
+//      (one workgroup per (problem, tile) work item);
+//   3. problems whose inner cycle ended (set E), and the newly admitted ones,
+//      get their correction u += d and their next FP64 residual (rounded to
+//      FP32, plus per-tile partial norms) in batched launches; one segmented
+//      reduction yields every norm needed (|g|^2 of the new ones, |r|^2 of E
+//      and the new ones) and one small device-to-host copy brings them back;
+//   4. the host decides for each of them exactly as the single-problem
+//      refinement does (converged, stagnated, or another inner cycle, halved
+//      when the last outer step contracted by less than 1/2); finished
+//      problems are staged out and their pool space is released.
+// Between cycle ends and admissions a step only enqueues its launches.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,27 +27,15 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/cj.h"
 #include "cj_internal.h"
-
-namespace {
-
-double centre_over_s(int stencil) {
-    switch (stencil) {
-    case 5: return 4.0;
-    case 9: return 20.0 / 6.0;
-    case 17: return 300.0 / 72.0;
-    default: return NAN;
-    }
-}
-
-size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
-
-}  // namespace
 
 // Set through cj_last_error's storage in runtime.cpp.
 extern "C" void cj_internal_set_error(const char* msg);
@@ -59,204 +54,576 @@ cj_status bfail(cj_status s, const std::string& msg) {
             return bfail(CJ_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));   \
     } while (0)
 
-struct Prob {
+double centre_over_s(int stencil) {
+    switch (stencil) {
+    case 5: return 4.0;
+    case 9: return 20.0 / 6.0;
+    case 17: return 300.0 / 72.0;
+    default: return NAN;
+    }
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+enum class State { Queued, New, Active, Done };
+
+// One problem: its host plan (schedules, layouts, geometry, pool footprint)
+// and its run state.
+struct Problem {
+    long long ticket = 0;
     int nx = 0, ny = 0, stencil = 9;
     double tol = 0.0, h = 0.0;
+    const double* f = nullptr;
+    double* u = nullptr;
     cj::Schedule s;                 // longest inner cycle (its M) and the kappa bounds
-    std::vector<float> w32;         // weights of the cycles M, M/2, ..., mmin
-    int mmin = 16;
+    std::vector<float> w32;         // FP32 weights of the cycles M, M/2, ..., mmin
+    int mmin = 16, K = 8;
     size_t w_offset(int m) const { return 2 * (size_t)s.M - 2 * (size_t)m; }
     cj::Layout L, L32;
-    cj::Tiles T;                    // single-sweep geometry (residual, correction, stage-in)
+    cj::Tiles T;                    // single-sweep geometry (stage-in, residual, correction), 256-lane tiles
     cj::Tiles TK;                   // blocked geometry (sweeps)
-    int K = 8;
-    size_t off_u = 0, off_g = 0, off_r = 0, off_d1 = 0, off_d2 = 0, off_w = 0;   // bytes into the slab
+    size_t bytes = 0;               // pool footprint
+    size_t off_u = 0, off_g = 0, off_r = 0, off_d1 = 0, off_d2 = 0, off_w = 0;   // within the block
+    // placement
+    size_t block = 0;
+    int slot = -1;
     // run state
-    bool active = false;
+    State state = State::Queued;
     int m = 0, j = 0, outer = 0, fails = 0;
     double g2 = 0.0, prev = 0.0, rr = 0.0, floor_est = 0.0;
     long long sweeps = 0;
     cj_status status = CJ_OK;
+    double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
 };
+
+// Builds the host plan of a problem; K from the requested depth (0: automatic).
+cj_status plan_problem(Problem& p, int Kreq, int tile_rows) {
+    std::string err;
+    if (!cj::make_schedule(p.stencil, p.nx, p.ny, p.tol, 0.0, 0, &p.s, &err)) return bfail(CJ_ERR_ARG, err);
+    const int R = p.stencil == 17 ? 2 : 1;
+    const int kdef = p.stencil == 17 ? 4 : 8;
+    p.K = Kreq ? std::min(Kreq, kdef) : kdef;
+    p.h = p.s.h;
+    p.mmin = std::max(16, p.K);
+    if (p.s.M < p.mmin && !cj::make_schedule(p.stencil, p.nx, p.ny, p.tol, 0.0, p.mmin, &p.s, &err))
+        return bfail(CJ_ERR_ARG, err);
+    p.w32.assign(2 * (size_t)p.s.M, 0.0f);
+    for (int m = p.s.M; m >= p.mmin; m /= 2) {
+        cj::Schedule sm;
+        if (!cj::make_schedule(p.stencil, p.nx, p.ny, p.tol, 0.0, m, &sm, &err)) return bfail(CJ_ERR_ARG, err);
+        for (int k = 0; k < m; ++k) p.w32[p.w_offset(m) + k] = (float)sm.w[k];
+    }
+    p.L = cj::make_layout(p.nx, p.ny, 8);
+    p.L32 = cj::make_layout(p.nx, p.ny, 4);
+    p.T = cj::make_tiles(p.nx, p.ny, 16);
+    p.T.width = 256;
+    p.T.tiles_x = (p.nx + 255) / 256;
+    p.TK = cj::make_tiles_k(p.nx, p.ny, p.K, R, tile_rows > 0 ? tile_rows : 64);
+    size_t off = 0;
+    p.off_u = off;  off += align256(p.L.elems * sizeof(double));
+    p.off_g = off;  off += align256(p.L.elems * sizeof(double));
+    p.off_r = off;  off += align256(p.L32.elems * sizeof(float));
+    p.off_d1 = off; off += align256(p.L32.elems * sizeof(float));
+    p.off_d2 = off; off += align256(p.L32.elems * sizeof(float));
+    p.off_w = off;  off += align256(p.w32.size() * sizeof(float));
+    p.bytes = off;
+    return CJ_OK;
+}
+
+// First-fit allocator over [0, size) of the device pool.
+struct PoolAlloc {
+    std::map<size_t, size_t> free_;   // offset -> length
+    size_t size = 0, used = 0;
+    void reset(size_t n) {
+        free_.clear();
+        size = n;
+        used = 0;
+        if (n) free_[0] = n;
+    }
+    bool alloc(size_t n, size_t* off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= n) {
+                *off = it->first;
+                const size_t rest = it->second - n, roff = it->first + n;
+                free_.erase(it);
+                if (rest) free_[roff] = rest;
+                used += n;
+                return true;
+            }
+        return false;
+    }
+    void release(size_t off, size_t n) {
+        used -= n;
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+template <typename T>
+struct DevBuf {   // device array with a pinned host mirror, grown at sync points
+    T* d = nullptr;
+    T* h = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t n) {
+        if (n <= cap) return hipSuccess;
+        const size_t c = std::max<size_t>(n, cap + cap / 2 + 16);
+        if (d) (void)hipFree(d);
+        if (h) (void)hipHostFree(h);
+        d = nullptr;
+        h = nullptr;
+        cap = 0;
+        hipError_t e = hipMalloc((void**)&d, c * sizeof(T));
+        if (e == hipSuccess) e = hipHostMalloc((void**)&h, c * sizeof(T), hipHostMallocDefault);
+        if (e == hipSuccess) cap = c;
+        return e;
+    }
+    void release() {
+        if (d) (void)hipFree(d);
+        if (h) (void)hipHostFree(h);
+        d = nullptr;
+        h = nullptr;
+        cap = 0;
+    }
+};
+
+const int kStencils[3] = {5, 9, 17};
+
+class Engine {
+public:
+    cj_options opt{};
+    int max_outer = 50;
+    int Kreq = 0;
+    size_t budget = 0;
+    int device = -1;
+    char* pool = nullptr;
+    PoolAlloc alloc;
+    std::vector<Problem*> slots;      // descriptor index -> problem (nullptr: free)
+    std::deque<Problem*> queue;       // submitted, not admitted (FIFO; a later one that fits may pass)
+    std::vector<Problem*> live;       // admitted, not finished
+    DevBuf<cj::BatchProblem> probs;
+    DevBuf<cj::BatchItem> work, work2;
+    DevBuf<int> seg;
+    DevBuf<double> norm;
+    double* part = nullptr;
+    size_t part_cap = 0;
+    int step_no = 0;
+    bool rebuild = true;
+    size_t group_size[3] = {0, 0, 0};
+    long long launches = 0, supersteps = 0;
+    double updates = 0.0;
+
+    ~Engine() { release(); }
+
+    void release() {
+        if (device >= 0) {
+            int cur = -1;
+            (void)hipGetDevice(&cur);
+            (void)hipSetDevice(device);
+            if (pool) (void)hipFree(pool);
+            if (part) (void)hipFree(part);
+            probs.release();
+            work.release();
+            work2.release();
+            seg.release();
+            norm.release();
+            if (cur >= 0) (void)hipSetDevice(cur);
+        }
+        pool = nullptr;
+        part = nullptr;
+        part_cap = 0;
+        device = -1;
+    }
+
+    cj_status bind() {
+        int dev = -1;
+        CJB_HIP(hipGetDevice(&dev));
+        if (device >= 0) {
+            if (dev != device) return bfail(CJ_ERR_DEVICE, "engine was first used on another device");
+            return CJ_OK;
+        }
+        hipError_t e = hipMalloc((void**)&pool, budget);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            pool = nullptr;
+            return bfail(e == hipErrorOutOfMemory ? CJ_ERR_NOMEM : CJ_ERR_HIP,
+                         std::string("pool allocation: ") + hipGetErrorString(e));
+        }
+        device = dev;
+        alloc.reset(budget);
+        return CJ_OK;
+    }
+
+    bool idle() const { return queue.empty() && live.empty(); }
+
+    cj::BatchProblem& desc(const Problem* p) { return probs.h[p->slot]; }
+
+    const float* wptr(const Problem* p) const {
+        return reinterpret_cast<const float*>(pool + p->block + p->off_w + p->w_offset(p->m) * sizeof(float));
+    }
+
+    // Descriptors go up with a wait, so that the pinned mirror can be edited
+    // again as soon as this returns.
+    cj_status upload_probs(hipStream_t stream) {
+        if (slots.empty()) return CJ_OK;
+        CJB_HIP(hipMemcpyAsync(probs.d, probs.h, slots.size() * sizeof(cj::BatchProblem), hipMemcpyHostToDevice,
+                               stream));
+        CJB_HIP(hipStreamSynchronize(stream));
+        return CJ_OK;
+    }
+
+    int take_slot(Problem* p) {
+        for (size_t i = 0; i < slots.size(); ++i)
+            if (!slots[i]) {
+                slots[i] = p;
+                return (int)i;
+            }
+        slots.push_back(p);
+        return (int)slots.size() - 1;
+    }
+
+    // Admits queued problems that fit in the pool (FIFO order; a later one may
+    // pass one that does not fit yet) and enqueues their stage-in.
+    cj_status admit(hipStream_t stream, std::vector<Problem*>* fresh) {
+        for (auto it = queue.begin(); it != queue.end();) {
+            Problem* p = *it;
+            size_t off = 0;
+            if (!alloc.alloc(p->bytes, &off)) {
+                ++it;
+                continue;
+            }
+            p->block = off;
+            p->slot = take_slot(p);
+            p->state = State::New;
+            p->t_admit = now_s();
+            fresh->push_back(p);
+            live.push_back(p);
+            it = queue.erase(it);
+        }
+        if (fresh->empty()) return CJ_OK;
+        if (probs.cap < slots.size()) {
+            // growing the descriptor array: keep the entries of the live problems
+            std::vector<cj::BatchProblem> keep(probs.h, probs.h + probs.cap);
+            CJB_HIP(hipStreamSynchronize(stream));
+            if (probs.ensure(slots.size()) != hipSuccess) return bfail(CJ_ERR_NOMEM, "descriptor allocation");
+            std::copy(keep.begin(), keep.end(), probs.h);
+        }
+        for (Problem* p : *fresh) {
+            char* base = pool + p->block;
+            // the corrections start zero and their Dirichlet rings stay zero
+            CJB_HIP(hipMemsetAsync(base + p->off_r, 0, p->off_w - p->off_r, stream));
+            CJB_HIP(hipMemcpyAsync(base + p->off_w, p->w32.data(), p->w32.size() * sizeof(float),
+                                   hipMemcpyHostToDevice, stream));
+            cj::BatchProblem& d = desc(p);
+            std::memset(&d, 0, sizeof(d));
+            d.u = reinterpret_cast<double*>(base + p->off_u);
+            d.g = reinterpret_cast<const double*>(base + p->off_g);
+            d.r32 = reinterpret_cast<float*>(base + p->off_r);
+            d.d1 = reinterpret_cast<float*>(base + p->off_d1);
+            d.d2 = reinterpret_cast<float*>(base + p->off_d2);
+            d.nx = p->nx;
+            d.ny = p->ny;
+            d.pitch = p->L.pitch;
+            d.pitch32 = p->L32.pitch;
+            d.tiles_x = p->T.tiles_x;
+            d.rows = p->T.rows;
+            d.strips_x = p->TK.tiles_x;
+            d.rows_k = p->TK.rows;
+            p->m = p->s.M;
+            p->j = p->outer = p->fails = 0;
+            p->sweeps = 0;
+            p->prev = p->rr = p->floor_est = p->g2 = 0.0;
+            d.w32 = wptr(p);
+        }
+        return CJ_OK;
+    }
+
+    cj_status ensure_part(size_t n, hipStream_t stream) {
+        if (n <= part_cap) return CJ_OK;
+        CJB_HIP(hipStreamSynchronize(stream));
+        if (part) (void)hipFree(part);
+        part = nullptr;
+        part_cap = 0;
+        const size_t c = std::max<size_t>(n, 1024);
+        CJB_HIP(hipMalloc((void**)&part, c * sizeof(double)));
+        part_cap = c;
+        return CJ_OK;
+    }
+
+    // The refinement decision (mirrors the single-problem loop).  True: continue.
+    bool decide(Problem& p) {
+        const double rr = p.rr;
+        const double q = p.outer >= 1 ? rr / p.prev : 0.0;
+        p.fails = (p.outer >= 1 && q > 0.9) ? p.fails + 1 : 0;
+        if (!std::isfinite(rr)) {
+            p.status = CJ_ERR_NONFINITE;
+        } else if (rr <= p.tol) {
+            p.status = CJ_OK;
+        } else if (p.fails >= 2) {
+            p.status = CJ_STAGNATED;
+            p.floor_est = rr < p.prev ? rr : p.prev;
+        } else if (p.outer >= max_outer) {
+            p.status = CJ_ERR_NOT_CONVERGED;
+        } else {
+            if (p.outer >= 1 && q > 0.5 && p.m > p.mmin) p.m /= 2;
+            p.prev = rr;
+            return true;
+        }
+        return false;
+    }
+
+    // One engine step (see the file comment).  Finished problems are appended to *done.
+    cj_status step(hipStream_t stream, std::vector<Problem*>* done) {
+        cj_status st;
+        if ((st = bind()) != CJ_OK) return st;
+        std::vector<Problem*> fresh;
+        if ((st = admit(stream, &fresh)) != CJ_OK) return st;
+        // stage-in of the admitted problems; their partials go first in `part`
+        size_t n_in = 0, n_res = 0;
+        for (Problem* p : fresh) n_in += p->T.count();
+        for (Problem* p : live) n_res += p->T.count();
+        if ((st = ensure_part(n_in + n_res, stream)) != CJ_OK) return st;
+        {
+            size_t pos = 0;
+            for (Problem* p : fresh) {
+                char* base = pool + p->block;
+                double* du = reinterpret_cast<double*>(base + p->off_u);
+                double* dg = reinterpret_cast<double*>(base + p->off_g);
+                const double scale = p->h * p->h / centre_over_s(p->stencil);
+                CJB_HIP(cj::launch_ring(p->L, p->u, du, du, dg, stream));
+                CJB_HIP(cj::launch_stage_in(p->L, p->T, p->f, p->u, scale, du, du, dg, part + pos, stream));
+                pos += p->T.count();
+            }
+        }
+        // batched sweeps of the active problems
+        bool any_active = false;
+        for (Problem* p : live) any_active = any_active || p->state == State::Active;
+        if (any_active) {
+            if (rebuild) {
+                size_t n = 0;
+                for (Problem* p : live)
+                    if (p->state == State::Active) n += p->TK.count();
+                if (work.cap < n) {
+                    CJB_HIP(hipStreamSynchronize(stream));
+                    if (work.ensure(n) != hipSuccess) return bfail(CJ_ERR_NOMEM, "work list allocation");
+                }
+                size_t pos = 0;
+                for (int gi = 0; gi < 3; ++gi) {
+                    const size_t start = pos;
+                    for (Problem* p : live)
+                        if (p->state == State::Active && p->stencil == kStencils[gi])
+                            for (int t = 0; t < p->TK.count(); ++t) work.h[pos++] = cj::BatchItem{p->slot, t};
+                    group_size[gi] = pos - start;
+                }
+                CJB_HIP(hipMemcpyAsync(work.d, work.h, pos * sizeof(cj::BatchItem), hipMemcpyHostToDevice, stream));
+                CJB_HIP(hipStreamSynchronize(stream));
+                rebuild = false;
+            }
+            size_t base = 0;
+            for (int gi = 0; gi < 3; ++gi) {
+                if (group_size[gi] == 0) continue;
+                int K = 0;
+                for (Problem* p : live)
+                    if (p->state == State::Active && p->stencil == kStencils[gi]) {
+                        K = p->K;
+                        break;
+                    }
+                CJB_HIP(cj::launch_batch_sweepk(kStencils[gi], K, probs.d, work.d + base, (int)group_size[gi],
+                                                step_no, stream));
+                ++launches;
+                base += group_size[gi];
+            }
+            ++step_no;
+            ++supersteps;
+        }
+        // cycle ends
+        std::vector<Problem*> R;
+        for (Problem* p : live) {
+            if (p->state != State::Active) continue;
+            ++p->j;
+            if (p->j * p->K == p->m) {
+                R.push_back(p);
+                p->sweeps += p->m;
+                updates += (double)p->nx * p->ny * p->m;
+                p->outer += 1;
+                desc(p).dcur = p->j & 1;   // launch j-1 wrote d[j & 1]
+            }
+        }
+        if (R.empty() && fresh.empty()) return CJ_OK;
+        const size_t n_ends = R.size();
+        R.insert(R.end(), fresh.begin(), fresh.end());
+        if ((st = upload_probs(stream)) != CJ_OK) return st;
+        // work list of R's single-sweep tiles per stencil group
+        size_t n2 = 0;
+        for (Problem* p : R) n2 += p->T.count();
+        if (work2.cap < n2) {
+            CJB_HIP(hipStreamSynchronize(stream));
+            if (work2.ensure(n2) != hipSuccess) return bfail(CJ_ERR_NOMEM, "work list allocation");
+        }
+        std::vector<Problem*> order;   // R in the order of their residual partials
+        std::pair<size_t, size_t> grp[3];
+        size_t pos = 0;
+        for (int gi = 0; gi < 3; ++gi) {
+            const size_t start = pos;
+            for (Problem* p : R)
+                if (p->stencil == kStencils[gi]) {
+                    for (int t = 0; t < p->T.count(); ++t) work2.h[pos++] = cj::BatchItem{p->slot, t};
+                    order.push_back(p);
+                }
+            grp[gi] = std::make_pair(start, pos - start);
+        }
+        CJB_HIP(hipMemcpyAsync(work2.d, work2.h, pos * sizeof(cj::BatchItem), hipMemcpyHostToDevice, stream));
+        for (int gi = 0; gi < 3; ++gi) {
+            const size_t start = grp[gi].first, cnt = grp[gi].second;
+            if (cnt == 0) continue;
+            // the correction of a fresh problem adds its zero d: exact, and keeps one work list
+            if (n_ends > 0)
+                CJB_HIP(cj::launch_batch_correct(kStencils[gi], probs.d, work2.d + start, (int)cnt, stream));
+            CJB_HIP(cj::launch_batch_residual(kStencils[gi], probs.d, work2.d + start, (int)cnt,
+                                              part + n_in + start, stream));
+        }
+        // segments: |g|^2 of the fresh ones (stage-in partials), then |r|^2 of `order`
+        const size_t nseg = fresh.size() + order.size();
+        if (seg.cap < nseg + 1 || norm.cap < nseg) {
+            CJB_HIP(hipStreamSynchronize(stream));
+            if (seg.ensure(nseg + 1) != hipSuccess || norm.ensure(nseg) != hipSuccess)
+                return bfail(CJ_ERR_NOMEM, "segment allocation");
+        }
+        {
+            int s = 0, p0 = 0;
+            for (Problem* p : fresh) {
+                seg.h[s++] = p0;
+                p0 += p->T.count();
+            }
+            for (Problem* p : order) {
+                seg.h[s++] = p0;
+                p0 += p->T.count();
+            }
+            seg.h[s] = p0;
+        }
+        CJB_HIP(hipMemcpyAsync(seg.d, seg.h, (nseg + 1) * sizeof(int), hipMemcpyHostToDevice, stream));
+        CJB_HIP(cj::launch_segmented_reduce(part, seg.d, (int)nseg, norm.d, stream));
+        CJB_HIP(hipMemcpyAsync(norm.h, norm.d, nseg * sizeof(double), hipMemcpyDeviceToHost, stream));
+        CJB_HIP(hipStreamSynchronize(stream));
+        for (size_t k = 0; k < fresh.size(); ++k) fresh[k]->g2 = norm.h[k];
+        for (size_t k = 0; k < order.size(); ++k) {
+            Problem* p = order[k];
+            p->rr = std::sqrt(norm.h[fresh.size() + k]) / std::sqrt(p->g2);
+        }
+        // decisions
+        for (Problem* p : R) {
+            bool cont = false;
+            if (p->state == State::New && !std::isfinite(p->g2)) {
+                p->status = CJ_ERR_NONFINITE;
+            } else if (p->state == State::New && p->g2 == 0.0) {
+                p->status = CJ_OK;
+                p->rr = 0.0;
+                CJB_HIP(hipMemsetAsync(p->u, 0, (size_t)p->nx * (size_t)p->ny * sizeof(double), stream));
+            } else {
+                cont = decide(*p);
+            }
+            if (cont) {
+                if (p->state == State::New) rebuild = true;
+                p->state = State::Active;
+                p->j = 0;
+                cj::BatchProblem& d = desc(p);
+                d.cycle_start = step_no;
+                d.w32 = wptr(p);
+            } else {
+                if (p->state == State::Active) rebuild = true;
+                if (p->g2 != 0.0 && std::isfinite(p->g2))
+                    CJB_HIP(cj::launch_stage_out(p->L, reinterpret_cast<double*>(pool + p->block + p->off_u), p->u,
+                                                 stream));
+                slots[p->slot] = nullptr;
+                alloc.release(p->block, p->bytes);
+                live.erase(std::find(live.begin(), live.end(), p));
+                p->state = State::Done;
+                p->t_done = now_s();
+                done->push_back(p);
+            }
+        }
+        // the wait here also completes the stage-outs before results are reported
+        return upload_probs(stream);
+    }
+
+    // Drops every queued and live problem (after an error), leaving the engine reusable.
+    void reset_run() {
+        queue.clear();
+        for (Problem* p : live) {
+            slots[p->slot] = nullptr;
+            alloc.release(p->block, p->bytes);
+        }
+        live.clear();
+        rebuild = true;
+    }
+};
+
+cj_status engine_options(const cj_options* opt, cj_options* o, int* Kreq) {
+    cj_options_init(o);
+    if (opt) *o = *opt;
+    for (int r : o->reserved)
+        if (r != 0) return bfail(CJ_ERR_ARG, "reserved option fields must be zero");
+    if (o->precision != CJ_PRECISION_F32_REFINE)
+        return bfail(CJ_ERR_ARG, "batched and served solves run FP32 sweeps inside FP64 refinement: set precision "
+                                 "= CJ_PRECISION_F32_REFINE");
+    if (o->M != 0 || o->inner_M != 0 || o->h != 0.0)
+        return bfail(CJ_ERR_ARG, "M, inner_M and h are per problem and automatic here (must be 0)");
+    if (o->max_cycles < 0 || o->tile_rows < 0) return bfail(CJ_ERR_ARG, "negative option");
+    *Kreq = o->sweeps_per_launch;
+    if (*Kreq != 0 && *Kreq != 2 && *Kreq != 4 && *Kreq != 8)
+        return bfail(CJ_ERR_ARG, "sweeps_per_launch must be 0 (automatic), 2, 4 or 8 here");
+    return CJ_OK;
+}
+
+cj_status check_problem(int nx, int ny, int stencil, double tol) {
+    if (stencil != 5 && stencil != 9 && stencil != 17) return bfail(CJ_ERR_ARG, "stencil must be 5, 9 or 17");
+    if (nx < 1 || ny < 1 || nx > (1 << 20) || ny > (1 << 20)) return bfail(CJ_ERR_ARG, "nx, ny out of range");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return bfail(CJ_ERR_ARG, "tol must be a finite positive number");
+    return CJ_OK;
+}
+
+void fill_result(const Problem& p, cj_result* r) {
+    std::memset(r, 0, sizeof(*r));
+    r->status = p.status;
+    r->cycles = p.outer;
+    r->sweeps = p.sweeps;
+    r->rel_residual = p.rr;
+    r->floor_estimate = p.status == CJ_STAGNATED ? p.floor_est : 0.0;
+    r->seconds = p.t_done - p.t_submit;
+}
 
 }  // namespace
 
 struct cj_batch_s {
-    std::vector<Prob> P;
-    cj_options opt;
-    int max_outer = 50;
-    int Kreq = 0;
-    // device
-    int device = -1;
-    char* slab = nullptr;
-    size_t slab_bytes = 0;
-    cj::BatchProblem* d_probs = nullptr;
-    cj::BatchItem* d_work = nullptr;     // sweep work list
-    cj::BatchItem* d_work2 = nullptr;    // cycle-end work list
-    double* d_part = nullptr;
-    int* d_seg = nullptr;
-    double* d_norm = nullptr;
-    size_t cap_items = 0, cap_parts = 0;
-    // pinned host mirrors
-    cj::BatchProblem* h_probs = nullptr;
-    cj::BatchItem* h_work = nullptr;
-    cj::BatchItem* h_work2 = nullptr;
-    int* h_seg = nullptr;
-    double* h_norm = nullptr;
+    Engine eng;
+    std::vector<Problem> P;
+    size_t total_bytes = 0;
 };
 
-namespace {
-
-void batch_release(cj_batch_s* b) {
-    if (b->device >= 0) {
-        int cur = -1;
-        (void)hipGetDevice(&cur);
-        (void)hipSetDevice(b->device);
-        for (void* d : {(void*)b->slab, (void*)b->d_probs, (void*)b->d_work, (void*)b->d_work2, (void*)b->d_part,
-                        (void*)b->d_seg, (void*)b->d_norm})
-            if (d) (void)hipFree(d);
-        for (void* h : {(void*)b->h_probs, (void*)b->h_work, (void*)b->h_work2, (void*)b->h_seg, (void*)b->h_norm})
-            if (h) (void)hipHostFree(h);
-        if (cur >= 0) (void)hipSetDevice(cur);
-    }
-    b->slab = nullptr;
-    b->d_probs = nullptr;
-    b->d_work = b->d_work2 = nullptr;
-    b->d_part = b->d_norm = nullptr;
-    b->d_seg = nullptr;
-    b->h_probs = nullptr;
-    b->h_work = b->h_work2 = nullptr;
-    b->h_seg = nullptr;
-    b->h_norm = nullptr;
-    b->device = -1;
-}
-
-cj_status batch_device(cj_batch_s* b, hipStream_t stream) {
-    int dev = -1;
-    CJB_HIP(hipGetDevice(&dev));
-    if (b->device >= 0) {
-        if (dev != b->device) return bfail(CJ_ERR_DEVICE, "batch was first used on another device");
-        return CJ_OK;
-    }
-    b->device = dev;
-    const size_t n = b->P.size();
-    size_t items = 0;
-    for (const Prob& p : b->P) items += (size_t)std::max(p.T.count(), p.TK.count());
-    b->cap_items = items;
-    b->cap_parts = items;
-    hipError_t e = hipMalloc((void**)&b->slab, b->slab_bytes);
-    if (e == hipSuccess) e = hipMalloc((void**)&b->d_probs, n * sizeof(cj::BatchProblem));
-    if (e == hipSuccess) e = hipMalloc((void**)&b->d_work, items * sizeof(cj::BatchItem));
-    if (e == hipSuccess) e = hipMalloc((void**)&b->d_work2, items * sizeof(cj::BatchItem));
-    if (e == hipSuccess) e = hipMalloc((void**)&b->d_part, items * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void**)&b->d_seg, (n + 1) * sizeof(int));
-    if (e == hipSuccess) e = hipMalloc((void**)&b->d_norm, n * sizeof(double));
-    if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_probs, n * sizeof(cj::BatchProblem), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_work, items * sizeof(cj::BatchItem), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_work2, items * sizeof(cj::BatchItem), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_seg, (n + 1) * sizeof(int), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_norm, n * sizeof(double), hipHostMallocDefault);
-    if (e != hipSuccess) {
-        batch_release(b);
-        (void)hipGetLastError();
-        return bfail(e == hipErrorOutOfMemory ? CJ_ERR_NOMEM : CJ_ERR_HIP,
-                     std::string("batch workspace allocation: ") + hipGetErrorString(e));
-    }
-    // corrections start and stay zero on their Dirichlet rings; upload the weight tables
-    CJB_HIP(hipMemsetAsync(b->slab, 0, b->slab_bytes, stream));
-    for (const Prob& p : b->P)
-        CJB_HIP(hipMemcpyAsync(b->slab + p.off_w, p.w32.data(), p.w32.size() * sizeof(float), hipMemcpyHostToDevice,
-                               stream));
-    CJB_HIP(hipStreamSynchronize(stream));
-    for (size_t i = 0; i < n; ++i) {
-        const Prob& p = b->P[i];
-        cj::BatchProblem& d = b->h_probs[i];
-        std::memset(&d, 0, sizeof(d));
-        d.u = reinterpret_cast<double*>(b->slab + p.off_u);
-        d.g = reinterpret_cast<const double*>(b->slab + p.off_g);
-        d.r32 = reinterpret_cast<float*>(b->slab + p.off_r);
-        d.d1 = reinterpret_cast<float*>(b->slab + p.off_d1);
-        d.d2 = reinterpret_cast<float*>(b->slab + p.off_d2);
-        d.w32 = reinterpret_cast<const float*>(b->slab + p.off_w);
-        d.nx = p.nx;
-        d.ny = p.ny;
-        d.pitch = p.L.pitch;
-        d.pitch32 = p.L32.pitch;
-        d.tiles_x = p.T.tiles_x;
-        d.rows = p.T.rows;
-        d.strips_x = p.TK.tiles_x;
-        d.rows_k = p.TK.rows;
-    }
-    return CJ_OK;
-}
-
-cj_status upload_probs(cj_batch_s* b, hipStream_t stream) {
-    CJB_HIP(hipMemcpyAsync(b->d_probs, b->h_probs, b->P.size() * sizeof(cj::BatchProblem), hipMemcpyHostToDevice,
-                           stream));
-    return CJ_OK;
-}
-
-// Cycle-end work for the problems in E: optional correction, then the residual
-// and per-problem norms (copied to h_norm; waits on the stream).
-cj_status cycle_end(cj_batch_s* b, const std::vector<int>& E, bool correct, hipStream_t stream) {
-    if (E.empty()) return CJ_OK;
-    for (int st : {5, 9, 17}) {
-        // work list of the single-sweep tiles of E's problems with this stencil
-        size_t n = 0;
-        for (int i : E)
-            if (b->P[i].stencil == st)
-                for (int t = 0; t < b->P[i].T.count(); ++t) b->h_work2[n++] = cj::BatchItem{i, t};
-        if (n == 0) continue;
-        CJB_HIP(hipMemcpyAsync(b->d_work2, b->h_work2, n * sizeof(cj::BatchItem), hipMemcpyHostToDevice, stream));
-        if (correct) CJB_HIP(cj::launch_batch_correct(st, b->d_probs, b->d_work2, (int)n, stream));
-        // partials of this group land at the group's offsets; the segments below
-        // index them in the same order
-        CJB_HIP(cj::launch_batch_residual(st, b->d_probs, b->d_work2, (int)n, b->d_part, stream));
-        // segments for this group
-        int nseg = 0, pos = 0;
-        std::vector<int> ids;
-        for (int i : E)
-            if (b->P[i].stencil == st) {
-                b->h_seg[nseg++] = pos;
-                pos += b->P[i].T.count();
-                ids.push_back(i);
-            }
-        b->h_seg[nseg] = pos;
-        CJB_HIP(hipMemcpyAsync(b->d_seg, b->h_seg, (nseg + 1) * sizeof(int), hipMemcpyHostToDevice, stream));
-        CJB_HIP(cj::launch_segmented_reduce(b->d_part, b->d_seg, nseg, b->d_norm, stream));
-        CJB_HIP(hipMemcpyAsync(b->h_norm, b->d_norm, nseg * sizeof(double), hipMemcpyDeviceToHost, stream));
-        CJB_HIP(hipStreamSynchronize(stream));
-        for (int k = 0; k < nseg; ++k) b->P[ids[k]].rr = std::sqrt(b->h_norm[k]) / std::sqrt(b->P[ids[k]].g2);
-    }
-    return CJ_OK;
-}
-
-// The refinement decision for one problem after a residual (mirrors the
-// single-problem loop).  Returns true if it continues with another inner cycle.
-bool decide(cj_batch_s* b, Prob& p) {
-    const double rr = p.rr;
-    const double q = p.outer >= 1 ? rr / p.prev : 0.0;
-    p.fails = (p.outer >= 1 && q > 0.9) ? p.fails + 1 : 0;
-    if (!std::isfinite(rr)) {
-        p.status = CJ_ERR_NONFINITE;
-    } else if (rr <= p.tol) {
-        p.status = CJ_OK;
-    } else if (p.fails >= 2) {
-        p.status = CJ_STAGNATED;
-        p.floor_est = rr < p.prev ? rr : p.prev;
-    } else if (p.outer >= b->max_outer) {
-        p.status = CJ_ERR_NOT_CONVERGED;
-    } else {
-        if (p.outer >= 1 && q > 0.5 && p.m > p.mmin) p.m /= 2;
-        p.prev = rr;
-        return true;
-    }
-    return false;
-}
-
-}  // namespace
+struct cj_server_s {
+    Engine eng;
+    hipStream_t stream = nullptr;
+    long long next_ticket = 1;
+    std::map<long long, Problem*> all;   // submitted and not yet reported
+};
 
 extern "C" {
+
+// ------------------------------------------------------------------ batches
 
 cj_status cj_batch_create(int n, const int* nx, const int* ny, const int* stencil, const double* tol,
                           const cj_options* opt, cj_batch_t* out) {
@@ -264,69 +631,34 @@ cj_status cj_batch_create(int n, const int* nx, const int* ny, const int* stenci
     *out = nullptr;
     if (n < 1 || !nx || !ny || !stencil || !tol) return bfail(CJ_ERR_ARG, "n >= 1 and non-NULL arrays required");
     cj_options o;
-    cj_options_init(&o);
-    if (opt) o = *opt;
-    for (int r : o.reserved)
-        if (r != 0) return bfail(CJ_ERR_ARG, "reserved option fields must be zero");
-    if (o.precision != CJ_PRECISION_F32_REFINE)
-        return bfail(CJ_ERR_ARG, "batches run FP32 sweeps inside FP64 refinement: set precision = "
-                                 "CJ_PRECISION_F32_REFINE");
-    if (o.M != 0 || o.inner_M != 0 || o.h != 0.0)
-        return bfail(CJ_ERR_ARG, "M, inner_M and h are per problem and automatic in a batch (must be 0)");
-    if (o.max_cycles < 0 || o.tile_rows < 0) return bfail(CJ_ERR_ARG, "negative option");
-    const int Kreq = o.sweeps_per_launch;
-    if (Kreq != 0 && Kreq != 2 && Kreq != 4 && Kreq != 8)
-        return bfail(CJ_ERR_ARG, "batch sweeps_per_launch must be 0 (automatic), 2, 4 or 8");
+    int Kreq = 0;
+    cj_status st;
+    if ((st = engine_options(opt, &o, &Kreq)) != CJ_OK) return st;
     cj_batch_s* b = new (std::nothrow) cj_batch_s();
     if (!b) return bfail(CJ_ERR_NOMEM, "host allocation");
-    b->opt = o;
-    b->Kreq = Kreq;
-    b->max_outer = o.max_cycles > 0 ? o.max_cycles : 50;
+    b->eng.opt = o;
+    b->eng.Kreq = Kreq;
+    b->eng.max_outer = o.max_cycles > 0 ? o.max_cycles : 50;
     b->P.resize(n);
-    size_t off = 0;
-    std::string err;
     for (int i = 0; i < n; ++i) {
-        Prob& p = b->P[i];
-        p.nx = nx[i];
-        p.ny = ny[i];
-        p.stencil = stencil[i];
-        p.tol = tol[i];
-        const int R = p.stencil == 17 ? 2 : 1;
-        const int kdef = p.stencil == 17 ? 4 : 8;
-        p.K = Kreq ? std::min(Kreq, kdef) : kdef;
-        if (!cj::make_schedule(p.stencil, p.nx, p.ny, p.tol, 0.0, 0, &p.s, &err)) {
+        Problem& p = b->P[i];
+        st = check_problem(nx[i], ny[i], stencil[i], tol[i]);
+        if (st == CJ_OK) {
+            p.nx = nx[i];
+            p.ny = ny[i];
+            p.stencil = stencil[i];
+            p.tol = tol[i];
+            st = plan_problem(p, Kreq, o.tile_rows);
+        }
+        if (st != CJ_OK) {
+            const std::string why = cj_last_error();
             delete b;
-            return bfail(CJ_ERR_ARG, "problem " + std::to_string(i) + ": " + err);
+            return bfail(st, "problem " + std::to_string(i) + ": " + why);
         }
-        p.h = p.s.h;
-        p.mmin = std::max(16, p.K);
-        if (p.s.M < p.mmin && !cj::make_schedule(p.stencil, p.nx, p.ny, p.tol, 0.0, p.mmin, &p.s, &err)) {
-            delete b;
-            return bfail(CJ_ERR_ARG, err);
-        }
-        p.w32.assign(2 * (size_t)p.s.M, 0.0f);
-        for (int m = p.s.M; m >= p.mmin; m /= 2) {
-            cj::Schedule sm;
-            if (!cj::make_schedule(p.stencil, p.nx, p.ny, p.tol, 0.0, m, &sm, &err)) {
-                delete b;
-                return bfail(CJ_ERR_ARG, err);
-            }
-            for (int k = 0; k < m; ++k) p.w32[p.w_offset(m) + k] = (float)sm.w[k];
-        }
-        p.L = cj::make_layout(p.nx, p.ny, 8);
-        p.L32 = cj::make_layout(p.nx, p.ny, 4);
-        p.T = cj::make_tiles(p.nx, p.ny, 16);
-        p.T.width = 256;   // batched single-sweep kernels use 256-lane tiles
-        p.T.tiles_x = (p.nx + 255) / 256;
-        p.TK = cj::make_tiles_k(p.nx, p.ny, p.K, R, o.tile_rows > 0 ? o.tile_rows : 64);
-        p.off_u = off;  off += align256(p.L.elems * sizeof(double));
-        p.off_g = off;  off += align256(p.L.elems * sizeof(double));
-        p.off_r = off;  off += align256(p.L32.elems * sizeof(float));
-        p.off_d1 = off; off += align256(p.L32.elems * sizeof(float));
-        p.off_d2 = off; off += align256(p.L32.elems * sizeof(float));
-        p.off_w = off;  off += align256(p.w32.size() * sizeof(float));
+        p.ticket = i;
+        b->total_bytes += p.bytes;
     }
-    b->slab_bytes = off;
+    b->eng.budget = b->total_bytes;
     *out = b;
     return CJ_OK;
 }
@@ -336,13 +668,13 @@ cj_status cj_batch_info(cj_batch_t b, int i, int* M, int* sweeps_per_launch, siz
     if (i < 0 || i >= (int)b->P.size()) return bfail(CJ_ERR_ARG, "problem index out of range");
     if (M) *M = b->P[i].s.M;
     if (sweeps_per_launch) *sweeps_per_launch = b->P[i].K;
-    if (workspace_bytes) *workspace_bytes = b->slab_bytes;
+    if (workspace_bytes) *workspace_bytes = b->total_bytes;
     return CJ_OK;
 }
 
 cj_status cj_batch_solve(cj_batch_t b, const double* const* f, double* const* u, void* stream_, cj_result* results,
                          cj_batch_stats* stats) {
-    const auto t0 = std::chrono::steady_clock::now();
+    const double t0 = now_s();
     if (!b) return bfail(CJ_ERR_ARG, "batch is NULL");
     if (!f || !u) return bfail(CJ_ERR_ARG, "f and u arrays are required");
     const int n = (int)b->P.size();
@@ -352,182 +684,156 @@ cj_status cj_batch_solve(cj_batch_t b, const double* const* f, double* const* u,
             return bfail(CJ_ERR_ARG, "problem " + std::to_string(i) + ": misaligned f or u");
     }
     hipStream_t stream = static_cast<hipStream_t>(stream_);
+    Engine& E = b->eng;
+    E.launches = E.supersteps = 0;
+    E.updates = 0.0;
+    for (int i = 0; i < n; ++i) {
+        Problem& p = b->P[i];
+        p.f = f[i];
+        p.u = u[i];
+        p.state = State::Queued;
+        p.status = CJ_OK;
+        p.t_submit = t0;
+        E.queue.push_back(&p);
+    }
+    std::vector<Problem*> done;
     cj_status st;
-    if ((st = batch_device(b, stream)) != CJ_OK) return st;
-
-    // ---- stage-in: every problem's u and g = D^{-1} f, with sums of g^2
-    {
-        int pos = 0;
-        for (int i = 0; i < n; ++i) {
-            Prob& p = b->P[i];
-            double* du = reinterpret_cast<double*>(b->slab + p.off_u);
-            double* dg = reinterpret_cast<double*>(b->slab + p.off_g);
-            const double scale = p.h * p.h / centre_over_s(p.stencil);
-            CJB_HIP(cj::launch_ring(p.L, u[i], du, du, dg, stream));
-            CJB_HIP(cj::launch_stage_in(p.L, p.T, f[i], u[i], scale, du, du, dg, b->d_part + pos, stream));
-            b->h_seg[i] = pos;
-            pos += p.T.count();
-        }
-        b->h_seg[n] = pos;
-        CJB_HIP(hipMemcpyAsync(b->d_seg, b->h_seg, (n + 1) * sizeof(int), hipMemcpyHostToDevice, stream));
-        CJB_HIP(cj::launch_segmented_reduce(b->d_part, b->d_seg, n, b->d_norm, stream));
-        CJB_HIP(hipMemcpyAsync(b->h_norm, b->d_norm, n * sizeof(double), hipMemcpyDeviceToHost, stream));
-        CJB_HIP(hipStreamSynchronize(stream));
-    }
-    std::vector<int> E;
-    for (int i = 0; i < n; ++i) {
-        Prob& p = b->P[i];
-        p.g2 = b->h_norm[i];
-        p.active = false;
-        p.outer = p.fails = 0;
-        p.sweeps = 0;
-        p.prev = p.rr = p.floor_est = 0.0;
-        p.m = p.s.M;
-        if (!std::isfinite(p.g2)) {
-            p.status = CJ_ERR_NONFINITE;
-        } else if (p.g2 == 0.0) {
-            p.status = CJ_OK;
-            CJB_HIP(hipMemsetAsync(u[i], 0, (size_t)p.nx * (size_t)p.ny * sizeof(double), stream));
-        } else {
-            E.push_back(i);
-        }
-        cj::BatchProblem& d = b->h_probs[i];
-        d.dnext = 0;
-        d.dcur = 0;
-        d.cycle_start = 0;
-        d.w32 = reinterpret_cast<const float*>(b->slab + p.off_w + p.w_offset(p.m) * sizeof(float));
-    }
-    // ---- initial residuals
-    CJB_HIP(hipStreamSynchronize(stream));
-    if ((st = upload_probs(b, stream)) != CJ_OK) return st;
-    if ((st = cycle_end(b, E, false, stream)) != CJ_OK) return st;
-    int step = 0;
-    long long launches = 0;
-    int supersteps = 0;
-    for (int i : E) {
-        Prob& p = b->P[i];
-        if (decide(b, p)) {
-            p.active = true;
-            p.j = 0;
-            cj::BatchProblem& d = b->h_probs[i];
-            d.cycle_start = step;
-            d.w32 = reinterpret_cast<const float*>(b->slab + p.off_w + p.w_offset(p.m) * sizeof(float));
+    while (!E.idle()) {
+        if ((st = E.step(stream, &done)) != CJ_OK) {
+            E.reset_run();
+            return st;
         }
     }
-    if ((st = upload_probs(b, stream)) != CJ_OK) return st;
-
-    // ---- super-steps
-    std::vector<size_t> group_n(3, 0);
-    const int stencils[3] = {5, 9, 17};
-    bool rebuild = true;
-    for (;;) {
-        bool any = false;
-        for (const Prob& p : b->P) any = any || p.active;
-        if (!any) break;
-        if (rebuild) {
-            // sweep work list: per stencil group, items of active problems, contiguous
-            size_t pos = 0;
-            for (int gi = 0; gi < 3; ++gi) {
-                const size_t start = pos;
-                for (int i = 0; i < n; ++i) {
-                    const Prob& p = b->P[i];
-                    if (!p.active || p.stencil != stencils[gi]) continue;
-                    for (int t = 0; t < p.TK.count(); ++t) b->h_work[pos++] = cj::BatchItem{i, t};
-                }
-                group_n[gi] = pos - start;
-            }
-            CJB_HIP(hipMemcpyAsync(b->d_work, b->h_work, pos * sizeof(cj::BatchItem), hipMemcpyHostToDevice, stream));
-            rebuild = false;
-        }
-        size_t base = 0;
-        for (int gi = 0; gi < 3; ++gi) {
-            if (group_n[gi] == 0) continue;
-            // the K of a group: all its problems share it (depends on the stencil only)
-            int K = 0;
-            for (const Prob& p : b->P)
-                if (p.stencil == stencils[gi]) {
-                    K = p.K;
-                    break;
-                }
-            CJB_HIP(cj::launch_batch_sweepk(stencils[gi], K, b->d_probs, b->d_work + base, (int)group_n[gi], step,
-                                            stream));
-            ++launches;
-            base += group_n[gi];
-        }
-        ++step;
-        ++supersteps;
-        E.clear();
-        for (int i = 0; i < n; ++i) {
-            Prob& p = b->P[i];
-            if (!p.active) continue;
-            ++p.j;
-            if (p.j * p.K == p.m) E.push_back(i);
-        }
-        if (E.empty()) continue;
-        for (int i : E) {
-            Prob& p = b->P[i];
-            p.sweeps += p.m;
-            p.outer += 1;
-            b->h_probs[i].dcur = p.j & 1;   // launch j-1 wrote d[j & 1]
-        }
-        if ((st = upload_probs(b, stream)) != CJ_OK) return st;
-        if ((st = cycle_end(b, E, true, stream)) != CJ_OK) return st;
-        for (int i : E) {
-            Prob& p = b->P[i];
-            if (decide(b, p)) {
-                p.j = 0;
-                cj::BatchProblem& d = b->h_probs[i];
-                d.cycle_start = step;
-                d.w32 = reinterpret_cast<const float*>(b->slab + p.off_w + p.w_offset(p.m) * sizeof(float));
-            } else {
-                p.active = false;
-                rebuild = true;
-            }
-        }
-        if ((st = upload_probs(b, stream)) != CJ_OK) return st;
-    }
-    // ---- stage-out
-    for (int i = 0; i < n; ++i) {
-        Prob& p = b->P[i];
-        if (p.g2 == 0.0 || !std::isfinite(p.g2)) continue;
-        CJB_HIP(cj::launch_stage_out(p.L, reinterpret_cast<double*>(b->slab + p.off_u), u[i], stream));
-    }
-    CJB_HIP(hipStreamSynchronize(stream));
-    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    const double secs = now_s() - t0;
     cj_status worst = CJ_OK;
     for (int i = 0; i < n; ++i) {
-        const Prob& p = b->P[i];
+        const Problem& p = b->P[i];
         if (results) {
-            cj_result& r = results[i];
-            std::memset(&r, 0, sizeof(r));
-            r.status = p.status;
-            r.cycles = p.outer;
-            r.sweeps = p.sweeps;
-            r.rel_residual = p.rr;
-            r.floor_estimate = p.status == CJ_STAGNATED ? p.floor_est : 0.0;
-            r.seconds = secs;
+            fill_result(p, &results[i]);
+            results[i].seconds = secs;
         }
         if (p.status != CJ_OK && worst == CJ_OK) worst = p.status;
     }
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
-        stats->supersteps = supersteps;
-        stats->launches = launches;
+        stats->supersteps = (int)E.supersteps;
+        stats->launches = E.launches;
         long long pts = 0;
-        for (const Prob& p : b->P) pts += (long long)p.nx * p.ny;
+        for (const Problem& p : b->P) pts += (long long)p.nx * p.ny;
         stats->points = pts;
+        stats->updates = E.updates;
         stats->seconds = secs;
-        double upd = 0.0;
-        for (const Prob& p : b->P) upd += (double)p.nx * p.ny * (double)p.sweeps;
-        stats->updates = upd;
     }
-    return worst == CJ_STAGNATED ? CJ_STAGNATED : (worst == CJ_OK ? CJ_OK : worst);
+    return worst;
 }
 
-void cj_batch_destroy(cj_batch_t b) {
-    if (!b) return;
-    batch_release(b);
-    delete b;
+void cj_batch_destroy(cj_batch_t b) { delete b; }
+
+// ------------------------------------------------------------------ server
+
+cj_status cj_server_create(const cj_options* opt, size_t hbm_budget_bytes, void* stream, cj_server_t* out) {
+    if (!out) return bfail(CJ_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (hbm_budget_bytes < ((size_t)1 << 20)) return bfail(CJ_ERR_ARG, "HBM budget below 1 MiB");
+    cj_options o;
+    int Kreq = 0;
+    cj_status st;
+    if ((st = engine_options(opt, &o, &Kreq)) != CJ_OK) return st;
+    cj_server_s* s = new (std::nothrow) cj_server_s();
+    if (!s) return bfail(CJ_ERR_NOMEM, "host allocation");
+    s->eng.opt = o;
+    s->eng.Kreq = Kreq;
+    s->eng.max_outer = o.max_cycles > 0 ? o.max_cycles : 50;
+    s->eng.budget = align256(hbm_budget_bytes);
+    s->stream = static_cast<hipStream_t>(stream);
+    *out = s;
+    return CJ_OK;
+}
+
+cj_status cj_server_submit(cj_server_t s, int nx, int ny, int stencil, double tol, const double* f, double* u,
+                           long long* ticket) {
+    if (!s || !ticket) return bfail(CJ_ERR_ARG, "server and ticket are required");
+    if (!f || !u || reinterpret_cast<uintptr_t>(f) % 8 || reinterpret_cast<uintptr_t>(u) % 8)
+        return bfail(CJ_ERR_ARG, "f and u must be non-NULL, 8-byte aligned device pointers");
+    cj_status st;
+    if ((st = check_problem(nx, ny, stencil, tol)) != CJ_OK) return st;
+    Problem* p = new (std::nothrow) Problem();
+    if (!p) return bfail(CJ_ERR_NOMEM, "host allocation");
+    p->nx = nx;
+    p->ny = ny;
+    p->stencil = stencil;
+    p->tol = tol;
+    if ((st = plan_problem(*p, s->eng.Kreq, s->eng.opt.tile_rows)) != CJ_OK) {
+        delete p;
+        return st;
+    }
+    if (p->bytes > s->eng.budget) {
+        delete p;
+        return bfail(CJ_ERR_NOMEM, "request needs more device memory than the whole HBM budget");
+    }
+    p->f = f;
+    p->u = u;
+    p->ticket = s->next_ticket++;
+    p->t_submit = now_s();
+    s->eng.queue.push_back(p);
+    s->all[p->ticket] = p;
+    *ticket = p->ticket;
+    return CJ_OK;
+}
+
+cj_status cj_server_step(cj_server_t s, long long* done_tickets, cj_result* done_results, int max_done,
+                         int* n_done) {
+    if (!s || !n_done) return bfail(CJ_ERR_ARG, "server and n_done are required");
+    *n_done = 0;
+    if (max_done < 0 || (max_done > 0 && (!done_tickets || !done_results)))
+        return bfail(CJ_ERR_ARG, "done arrays are required when max_done > 0");
+    std::vector<Problem*> done;
+    cj_status st = CJ_OK;
+    if (!s->eng.idle()) st = s->eng.step(s->stream, &done);
+    if (st != CJ_OK) {
+        // fail every request that was in flight; report them as errors
+        for (Problem* p : s->eng.live) {
+            p->status = st;
+            p->state = State::Done;
+            p->t_done = now_s();
+        }
+        for (Problem* p : s->eng.queue) {
+            p->status = st;
+            p->state = State::Done;
+            p->t_done = now_s();
+        }
+        s->eng.reset_run();
+    }
+    int k = 0;
+    for (auto it = s->all.begin(); it != s->all.end() && k < max_done;) {
+        Problem* p = it->second;
+        if (p->state != State::Done) {
+            ++it;
+            continue;
+        }
+        done_tickets[k] = p->ticket;
+        fill_result(*p, &done_results[k]);
+        ++k;
+        delete p;
+        it = s->all.erase(it);
+    }
+    *n_done = k;
+    return st;
+}
+
+cj_status cj_server_stats(cj_server_t s, int* active, int* queued, size_t* bytes_in_use) {
+    if (!s) return bfail(CJ_ERR_ARG, "server is NULL");
+    if (active) *active = (int)s->eng.live.size();
+    if (queued) *queued = (int)s->eng.queue.size();
+    if (bytes_in_use) *bytes_in_use = s->eng.alloc.used;
+    return CJ_OK;
+}
+
+void cj_server_destroy(cj_server_t s) {
+    if (!s) return;
+    if (s->stream && s->eng.device >= 0) (void)hipStreamSynchronize(s->stream);
+    for (auto& kv : s->all) delete kv.second;
+    delete s;
 }
 
 }  // extern "C"

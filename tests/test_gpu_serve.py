@@ -1,0 +1,91 @@
+"""GPU tests of continuous-batching serving (cj_server_*): requests arrive while
+others run, are admitted as the HBM budget frees up, and each result is the same
+alone and in the mix (bit for bit: a request's arithmetic does not depend on its
+neighbours in the shared launches), and meets its tolerance per the oracle."""
+import numpy as np
+import pytest
+
+from oracle import cjm
+from paper_1705_00103_amd import cj, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _requests(n, seed):
+    rng = np.random.default_rng(seed)
+    shapes = inputs.log_uniform_shapes(n, seed=seed, lo=16, hi=300)
+    stencils = [int(rng.choice([5, 9])) for _ in range(n)]
+    tols = [float(rng.choice([1e-6, 1e-8, 1e-10])) for _ in range(n)]
+    return shapes, stencils, tols
+
+
+def _alone(torch, nx, ny, st, tol, f):
+    """The same request served alone by a fresh server."""
+    srv = cj.Server(hbm_budget_bytes=1 << 28)
+    u = torch.zeros(ny, nx, dtype=torch.float64, device="cuda")
+    tk = srv.submit(nx, ny, st, tol, f, u)
+    done = []
+    while not done:
+        done = srv.step()
+    srv.destroy()
+    assert done[0][0] == tk
+    return u.cpu().numpy(), done[0][1]
+
+
+def test_results_are_the_same_alone_and_in_the_mix(torch_cuda):
+    torch = torch_cuda
+    n = 14
+    shapes, stencils, tols = _requests(n, seed=11)
+    hf = [inputs.gaussian_bumps_rhs(nx, ny, seed=300 + i) for i, (nx, ny) in enumerate(shapes)]
+    fs = [torch.from_numpy(f).to("cuda") for f in hf]
+    us = [torch.zeros_like(f) for f in fs]
+    # a budget of about three mid-sized requests forces queueing and admission on release
+    srv = cj.Server(hbm_budget_bytes=3 * 300 * 300 * 44)
+    tickets = {}
+    results = {}
+    steps = 0
+    # arrivals interleaved with steps: submit two requests every third step
+    pending = list(range(n))
+    while pending or len(results) < n:
+        if pending and steps % 3 == 0:
+            for _ in range(2):
+                if pending:
+                    i = pending.pop(0)
+                    nx, ny = shapes[i]
+                    tickets[srv.submit(nx, ny, stencils[i], tols[i], fs[i], us[i])] = i
+        for tk, r in srv.step():
+            results[tickets[tk]] = r
+        steps += 1
+        assert steps < 200000
+    st = srv.stats()
+    assert st["active"] == 0 and st["queued"] == 0 and st["bytes_in_use"] == 0
+    srv.destroy()
+    for i in range(n):
+        nx, ny = shapes[i]
+        got = us[i].cpu().numpy()
+        alone, ra = _alone(torch, nx, ny, stencils[i], tols[i], fs[i])
+        r = results[i]
+        print(i, (nx, ny), stencils[i], tols[i], r["status"], r["cycles"], ra["cycles"], flush=True)
+        assert r["status"] == ra["status"] == "ok"
+        assert (r["cycles"], r["sweeps"]) == (ra["cycles"], ra["sweeps"])
+        assert np.array_equal(got, alone)
+        assert cjm.relative_residual(stencils[i], hf[i], got, nx, ny) <= tols[i] * 1.01
+
+
+def test_oversized_request_is_refused(torch_cuda):
+    torch = torch_cuda
+    srv = cj.Server(hbm_budget_bytes=1 << 20)
+    f = torch.ones(512, 512, dtype=torch.float64, device="cuda")
+    u = torch.zeros_like(f)
+    with pytest.raises(cj.CJError) as e:
+        srv.submit(512, 512, 9, 1e-8, f, u)
+    assert e.value.code == cj.CJ_ERR_NOMEM
+    srv.destroy()
