@@ -88,7 +88,10 @@ typedef struct {
     int    precision;          /* cj_precision; 0 = CJ_PRECISION_F64 */
     int    inner_M;            /* CJ_PRECISION_F32_REFINE: inner cycle length (a power of
                                   two); 0 = the automatic M.  Must be 0 otherwise. */
-    int    reserved[6];        /* must be zero */
+    int    graph;              /* FP64 solves: replay each cycle's plain launches as one HIP
+                                  graph; 0 = automatic (grids of at most 2^22 points, where
+                                  launch overhead matters), 1 = always, -1 = never */
+    int    reserved[5];        /* must be zero */
 } cj_options;
 
 /* Outcome of a solve. */

@@ -45,7 +45,7 @@ class Options(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int), ("max_cycles", ctypes.c_int),
                 ("sweeps_per_launch", ctypes.c_int), ("tile_rows", ctypes.c_int),
                 ("h", ctypes.c_double), ("precision", ctypes.c_int), ("inner_M", ctypes.c_int),
-                ("reserved", ctypes.c_int * 6)]
+                ("graph", ctypes.c_int), ("reserved", ctypes.c_int * 5)]
 
 
 class Result(ctypes.Structure):
@@ -155,12 +155,12 @@ class Plan:
     """Owns a cj_plan_t.  Attributes mirror cj_plan_info."""
 
     def __init__(self, nx, ny, stencil=9, tol=1e-10, M=0, max_cycles=0, sweeps_per_launch=0,
-                 tile_rows=0, h=0.0, bc=0, precision=F64, inner_M=0):
+                 tile_rows=0, h=0.0, bc=0, precision=F64, inner_M=0, graph=0):
         L = lib()
         o = Options()
         L.cj_options_init(ctypes.byref(o))
         o.M, o.max_cycles, o.sweeps_per_launch, o.tile_rows, o.h = M, max_cycles, sweeps_per_launch, tile_rows, h
-        o.precision, o.inner_M = precision, inner_M
+        o.precision, o.inner_M, o.graph = precision, inner_M, graph
         self.precision = precision
         handle = ctypes.c_void_p()
         _check(L.cj_plan_ex(nx, ny, stencil, bc, tol, ctypes.byref(o), ctypes.byref(handle)), "cj_plan_ex")

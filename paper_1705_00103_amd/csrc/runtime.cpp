@@ -95,6 +95,13 @@ struct cj_plan_s {
     float* D2 = nullptr;
     float* W32 = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};   // bracket the plain sweeps of a cycle
+    // The plain launches of an FP64 cycle (all but the first, norm-fused one),
+    // captured once as a graph on a private stream and replayed every cycle.
+    bool use_graph = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    long long graph_launches = 0;
     bool mixed() const { return precision == CJ_PRECISION_F32_REFINE; }
     size_t workspace_bytes() const {
         size_t b = 3 * L.elems * sizeof(double) + (size_t)s.M * sizeof(double) +
@@ -122,11 +129,17 @@ void release(cj_plan_s* p) {
         if (p->host_slot) (void)hipHostFree(p->host_slot);
         for (hipEvent_t& e : p->ev)
             if (e) (void)hipEventDestroy(e);
+        if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
         if (cur >= 0) (void)hipSetDevice(cur);
     }
     p->A = p->B = p->G = p->W = p->part = p->scalar = p->host_slot = nullptr;
     p->R32 = p->D1 = p->D2 = p->W32 = nullptr;
     p->ev[0] = p->ev[1] = nullptr;
+    p->graph_exec = nullptr;
+    p->graph = nullptr;
+    p->cap_stream = nullptr;
     p->device = -1;
 }
 
@@ -247,6 +260,32 @@ cj_status enqueue_f32(cj_plan_s* p, int m, long long first, long long n, float**
                                  nxt, stream, nullptr, launches);
 }
 
+// Captures the plain launches of one FP64 cycle (sweeps k0 .. M-1, starting
+// from buffer B) into p->graph_exec.  The cycle has M/K launches in all; with
+// M/K even the captured part has an odd count and ends in A, where the next
+// cycle starts, so the same graph serves every cycle.
+cj_status capture_cycle(cj_plan_s* p, long long k0) {
+    if (p->graph_exec) return CJ_OK;
+    CJ_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    CJ_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    double* cur = p->B;
+    double* nxt = p->A;
+    long long launches = 0;
+    cj_status st = enqueue_f64(p, k0, p->s.M - k0, &cur, &nxt, p->cap_stream, nullptr, &launches);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+    if (st != CJ_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(CJ_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    p->graph = g;
+    CJ_HIP(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
+    p->graph_launches = launches;
+    if (cur != p->A) return fail(CJ_ERR_HIP, "captured cycle does not end in the start buffer");
+    return CJ_OK;
+}
+
 // The FP64 CJM loop (see the file comment).  On return *out_buf is the buffer
 // holding the answer.
 cj_status solve_f64(cj_plan_s* p, double gnorm, hipStream_t stream, cj_result* r, double** out_buf) {
@@ -297,8 +336,17 @@ cj_status solve_f64(cj_plan_s* p, double gnorm, hipStream_t stream, cj_result* r
         prev = rr;
         if (M > k0) {
             timed_launches = 0;
+            const bool graph_ok = p->use_graph && k0 == p->K && cur == p->B;
+            if (graph_ok && (st = capture_cycle(p, k0)) != CJ_OK) return st;
             CJ_HIP(hipEventRecord(p->ev[0], stream));
-            if ((st = enqueue_f64(p, k0, M - k0, &cur, &nxt, stream, nullptr, &timed_launches)) != CJ_OK) return st;
+            if (graph_ok) {
+                CJ_HIP(hipGraphLaunch(p->graph_exec, stream));
+                timed_launches = p->graph_launches;
+                std::swap(cur, nxt);   // the graph ends in A (see capture_cycle)
+            } else {
+                if ((st = enqueue_f64(p, k0, M - k0, &cur, &nxt, stream, nullptr, &timed_launches)) != CJ_OK)
+                    return st;
+            }
             CJ_HIP(hipEventRecord(p->ev[1], stream));
             timed = true;
         }
@@ -438,6 +486,16 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol, const cj_o
         if (p->K > 1) p->TK = cj::make_tiles_k(nx, ny, p->K, R, o.tile_rows);
     }
     p->D = centre_over_s(stencil) / (p->s.h * p->s.h);
+    if (o.graph < -1 || o.graph > 1) {
+        delete p;
+        return fail(CJ_ERR_ARG, "graph must be -1, 0 or 1");
+    }
+    {
+        // graphs need whole K-launches per cycle with an even launch count
+        const bool shape_ok = !mixed && p->K > 1 && p->s.M % p->K == 0 && (p->s.M / p->K) % 2 == 0;
+        const bool small = (long long)nx * ny <= (1LL << 22);
+        p->use_graph = shape_ok && (o.graph == 1 || (o.graph == 0 && small));
+    }
     *out = p;
     return CJ_OK;
 }

@@ -256,3 +256,26 @@ def test_full_size_solve_against_exact_solution(torch_cuda):
     assert abs(rr - r["rel_residual"]) <= 1e-3 * rr + noise
     assert rr <= 5e-10          # FP64 floor at this size: the stored iterate cannot do better
     assert err <= 1e-8
+
+
+@pytest.mark.parametrize("st,nx,ny", [(9, 128, 128), (5, 300, 77), (17, 200, 150), (9, 1000, 1000)])
+def test_graph_replayed_cycles_match_eager_launches(torch_cuda, st, nx, ny):
+    """Each cycle's plain launches replayed as one captured graph give the same bits
+    as launching them one by one; the graph is replayed across cycles and across
+    solves, with eager work (another plan's solve) in between."""
+    torch = torch_cuda
+    f = _dev(torch, inputs.gaussian_bumps_rhs(nx, ny, seed=31))
+    pg = cj.plan(nx, ny, st, 1e-10, graph=1)
+    pe = cj.plan(nx, ny, st, 1e-10, graph=-1)
+    ref = None
+    for rep in range(3):
+        ue = torch.zeros(ny, nx, dtype=torch.float64, device="cuda")
+        re = cj.solve(pe, f, ue)
+        ug = torch.zeros(ny, nx, dtype=torch.float64, device="cuda")
+        rg = cj.solve(pg, f, ug)
+        assert (rg["status"], rg["cycles"]) == (re["status"], re["cycles"])
+        assert rg["cycles"] >= 2
+        assert torch.equal(ug, ue)
+        if ref is None:
+            ref = ue.clone()
+        assert torch.equal(ug, ref)
