@@ -38,6 +38,17 @@ Readings (the paper does not fix these; each is pinned by the tests):
       after the predicted cycle count, a cycle fails to halve the residual;
       report "not_converged" after max_cycles (default predicted + 4) cycles.
       A zero right-hand side has the solution u = 0.
+  R9  Non-homogeneous Dirichlet data (the paper's test problem takes them from
+      the analytic solution) travel in a frame of width G around the interior,
+      G = the stencil radius: for the 17-point stencil the second layer holds
+      prescribed ghost values instead of the reflection of R3.  The relative
+      residual is then taken against the residual of the zero interior, i.e.
+      the norm of the lifted right-hand side f - A_IB u_B.
+  R10 Jacobi, the paper's reference method, is the same sweep with omega = 1.
+      It is checked every M sweeps, M = 2^p the largest power of two not above
+      max(1, n_J / 32), where n_J = ceil(ln(1/tol) / -ln(1 - kappa_min)) sweeps
+      meet tol under the bound (1 - kappa_min)^n; the predicted check count is
+      ceil(n_J / M) and the stopping rule is R8's.
 """
 import ctypes
 import math
@@ -53,6 +64,8 @@ STENCILS = (5, 9, 17)
 KAPPA_MAX = {5: 2.0, 9: 8.0 / 5.0, 17: 128.0 / 75.0}
 # Stencil radius: the 17-point stencil reaches two nodes out.
 RADIUS = {5: 1, 9: 1, 17: 2}
+# Boundary data (R3, R9).
+BC_ZERO, BC_FRAME = 0, 1
 
 
 def lib():
@@ -131,6 +144,34 @@ def pad(u, nx, ny):
 
 def unpad(p, nx, ny):
     return np.ascontiguousarray(p[2:ny + 2, 2:nx + 2])
+
+
+def pad_frame(uf, nx, ny, stencil):
+    """Frame array (ny + 2G, nx + 2G) over nodes 1-G .. n+G (R9) -> padded
+    (ny+4, nx+4) array; nodes beyond the frame (the second ring of the 5- and
+    9-point stencils, which they never read) are zero."""
+    G = RADIUS[stencil]
+    uf = np.asarray(uf, dtype=np.float64)
+    if uf.shape != (ny + 2 * G, nx + 2 * G):
+        raise ValueError("frame array must be (ny + 2G, nx + 2G) = %r" % ((ny + 2 * G, nx + 2 * G),))
+    p = np.zeros((ny + 4, nx + 4), dtype=np.float64)
+    p[2 - G:ny + 2 + G, 2 - G:nx + 2 + G] = uf
+    return p
+
+
+def unpad_frame(p, nx, ny, stencil):
+    G = RADIUS[stencil]
+    return np.ascontiguousarray(p[2 - G:ny + 2 + G, 2 - G:nx + 2 + G])
+
+
+def _padded(u, nx, ny, stencil, bc):
+    return pad_frame(u, nx, ny, stencil) if bc == BC_FRAME else pad(u, nx, ny)
+
+
+def _zero_interior(p, nx, ny):
+    z = p.copy()
+    z[2:ny + 2, 2:nx + 2] = 0.0
+    return z
 
 
 # ----------------------------------------------------------------------------- plan
@@ -212,15 +253,45 @@ def weights(kmin, kmax, M):
     return [weight(t, M, kmin, kmax) for t in lf_order(M)]
 
 
+def jacobi_sweeps_needed(kmin, tol):
+    """n_J of R10: sweeps after which (1 - kappa_min)^n <= tol."""
+    if tol >= 1.0:
+        return 1
+    return max(1, math.ceil(math.log(1.0 / tol) / -math.log1p(-kmin)))
+
+
+def jacobi_check(kmin, tol, max_log2=24):
+    """(M, predicted checks) of R10."""
+    nj = jacobi_sweeps_needed(kmin, tol)
+    M = 1
+    while 2 * M <= max(1, nj // 32) and M < (1 << max_log2):
+        M *= 2
+    return M, math.ceil(nj / M)
+
+
 class Plan:
-    def __init__(self, nx, ny, stencil, tol, M=None, h=None):
+    def __init__(self, nx, ny, stencil, tol, M=None, h=None, method="chebyshev", bc=BC_ZERO):
         if nx < 1 or ny < 1:
             raise ValueError("nx, ny must be >= 1")
         if not (tol > 0.0):
             raise ValueError("tol must be > 0")
+        if method not in ("chebyshev", "jacobi"):
+            raise ValueError("method must be 'chebyshev' or 'jacobi'")
+        if bc not in (BC_ZERO, BC_FRAME):
+            raise ValueError("bc must be BC_ZERO or BC_FRAME")
         self.nx, self.ny, self.stencil, self.tol = nx, ny, stencil, tol
+        self.method, self.bc = method, bc
         self.h = spacing(nx, ny) if h is None else float(h)
         self.kmin, self.kmax = kappa_bounds(stencil, nx, ny)
+        if method == "jacobi":
+            # R10: omega = 1 throughout; M is the check interval
+            if M is None:
+                self.M, self.cycles_pred = jacobi_check(self.kmin, tol)
+            else:
+                self.M, self.cycles_pred = M, math.ceil(jacobi_sweeps_needed(self.kmin, tol) / M)
+            self.weights = [1.0] * self.M
+            self.rho = math.exp(self.M * math.log1p(-self.kmin))   # (1 - kappa_min)^M
+            return
         b = beta(self.kmin, self.kmax)
         if M is None:
             self.M, self.cycles_pred = choose_cycle(self.kmin, self.kmax, tol)
@@ -230,20 +301,23 @@ class Plan:
         self.rho = math.exp(-log_cosh(self.M * b))   # Chebyshev bound per cycle
 
 
-def plan(nx, ny, stencil, tol, M=None, h=None):
-    return Plan(nx, ny, stencil, tol, M=M, h=h)
+def plan(nx, ny, stencil, tol, M=None, h=None, method="chebyshev", bc=BC_ZERO):
+    return Plan(nx, ny, stencil, tol, M=M, h=h, method=method, bc=bc)
 
 
 # ----------------------------------------------------------------------------- loops
 
 
 def sweep(p, f, u_in, u_out, omega, region=None):
-    """One weighted Jacobi sweep of the padded iterate u_in into u_out (ring refilled)."""
+    """One weighted Jacobi sweep of the padded iterate u_in into u_out.  With
+    homogeneous data the ring of u_out is refilled (zeros, reflections); with a
+    frame (R9) it is data, and both buffers already hold it."""
     nx, ny = p.nx, p.ny
     i0, i1, j0, j1 = region if region is not None else (1, nx, 1, ny)
     L = lib()
     L.cjo_sweep(nx, ny, p.stencil, p.h, _ptr(f), _ptr(u_in), _ptr(u_out), omega, i0, i1, j0, j1)
-    L.cjo_fill_ring(nx, ny, _ptr(u_out))
+    if p.bc == BC_ZERO:
+        L.cjo_fill_ring(nx, ny, _ptr(u_out))
 
 
 def sumsq(x):
@@ -266,30 +340,51 @@ def apply(stencil, u, nx, ny, h=None):
     return out
 
 
-def relative_residual(stencil, f, u, nx, ny, h=None):
-    """||f - A u||_2 / ||f||_2 (R8), accumulated serially in FP64."""
-    p = Plan(nx, ny, stencil, 1.0, M=1, h=h)
+def rhs_norm(p, f, u_pad):
+    """The denominator of the relative residual: ||f|| for homogeneous data
+    (R8), the residual norm of the zero interior inside the frame for a frame
+    (R9)."""
+    if p.bc == BC_FRAME:
+        return math.sqrt(residual_sumsq(p, f, _zero_interior(u_pad, p.nx, p.ny)))
+    return math.sqrt(sumsq(f))
+
+
+def relative_residual(stencil, f, u, nx, ny, h=None, bc=BC_ZERO):
+    """||f - A u||_2 / ||f - A u_0||_2 with u_0 the zero interior (R8, R9),
+    accumulated serially in FP64.  With bc = BC_FRAME, u is the frame array."""
+    p = Plan(nx, ny, stencil, 1.0, M=1, h=h, bc=bc)
     f = np.ascontiguousarray(f, dtype=np.float64).reshape(ny, nx)
-    fn = math.sqrt(sumsq(f))
-    return math.sqrt(residual_sumsq(p, f, pad(u, nx, ny))) / fn
+    up = _padded(u, nx, ny, stencil, bc)
+    return math.sqrt(residual_sumsq(p, f, up)) / rhs_norm(p, f, up)
 
 
-def solve(f, nx, ny, stencil, tol, M=None, u0=None, max_cycles=None, h=None):
-    """Full CJM solve (R8).  Returns a dict: u, status, cycles, sweeps, relres, history, plan."""
-    p = Plan(nx, ny, stencil, tol, M=M, h=h)
+def solve(f, nx, ny, stencil, tol, M=None, u0=None, max_cycles=None, h=None, method="chebyshev", bc=BC_ZERO):
+    """Full solve (R8; R9 with bc = BC_FRAME, where u0 is the frame array and is
+    required; R10 with method = 'jacobi').  Returns a dict: u (the frame array
+    for a frame), status, cycles, sweeps, relres, history, plan."""
+    p = Plan(nx, ny, stencil, tol, M=M, h=h, method=method, bc=bc)
     f = np.ascontiguousarray(f, dtype=np.float64).reshape(ny, nx)
     if max_cycles is None:
         max_cycles = p.cycles_pred + 4
-    fnorm = math.sqrt(sumsq(f))
+    if bc == BC_FRAME:
+        if u0 is None:
+            raise ValueError("a frame solve needs u0 (the frame array with the boundary data)")
+        a = pad_frame(u0, nx, ny, stencil)
+    else:
+        a = pad(np.zeros((ny, nx)) if u0 is None else u0, nx, ny)
+
+    def result(pad_arr):
+        return unpad_frame(pad_arr, nx, ny, stencil) if bc == BC_FRAME else unpad(pad_arr, nx, ny)
+
+    fnorm = rhs_norm(p, f, a)
     out = dict(plan=p, cycles=0, sweeps=0, history=[])
     if not math.isfinite(fnorm):
-        out.update(u=np.full((ny, nx), np.nan), status="nonfinite", relres=float("nan"))
+        out.update(u=np.full(result(a).shape, np.nan), status="nonfinite", relres=float("nan"))
         return out
     if fnorm == 0.0:
-        out.update(u=np.zeros((ny, nx)), status="ok", relres=0.0)
+        out.update(u=result(_zero_interior(a, nx, ny)), status="ok", relres=0.0)
         return out
-    a = pad(np.zeros((ny, nx)) if u0 is None else u0, nx, ny)
-    b = np.zeros_like(a)
+    b = a.copy()
     hist = out["history"]
     c = 0
     while True:
@@ -311,32 +406,38 @@ def solve(f, nx, ny, stencil, tol, M=None, u0=None, max_cycles=None, h=None):
             sweep(p, f, a, b, w)
             a, b = b, a
         c += 1
-    out.update(u=unpad(a, nx, ny), status=status, relres=hist[-1], cycles=c, sweeps=c * p.M)
+    out.update(u=result(a), status=status, relres=hist[-1], cycles=c, sweeps=c * p.M)
     return out
 
 
-def run_sweeps(f, nx, ny, stencil, tol, n, M=None, u0=None, h=None):
-    """The iterate after the first n sweeps of the schedule (weights taken cyclically)."""
-    p = Plan(nx, ny, stencil, tol, M=M, h=h)
+def run_sweeps(f, nx, ny, stencil, tol, n, M=None, u0=None, h=None, method="chebyshev", bc=BC_ZERO):
+    """The iterate after the first n sweeps of the schedule (weights taken
+    cyclically); the frame array for bc = BC_FRAME (u0 required then)."""
+    p = Plan(nx, ny, stencil, tol, M=M, h=h, method=method, bc=bc)
     f = np.ascontiguousarray(f, dtype=np.float64).reshape(ny, nx)
-    a = pad(np.zeros((ny, nx)) if u0 is None else u0, nx, ny)
-    b = np.zeros_like(a)
+    if bc == BC_FRAME:
+        a = pad_frame(u0, nx, ny, stencil)
+    else:
+        a = pad(np.zeros((ny, nx)) if u0 is None else u0, nx, ny)
+    b = a.copy()
     for k in range(n):
         sweep(p, f, a, b, p.weights[k % p.M])
         a, b = b, a
-    return unpad(a, nx, ny)
+    return unpad_frame(a, nx, ny, stencil) if bc == BC_FRAME else unpad(a, nx, ny)
 
 
-def sampled_sweeps(f, u0, nx, ny, stencil, tol, n, points, M=None, h=None, first=0):
+def sampled_sweeps(f, u0, nx, ny, stencil, tol, n, points, M=None, h=None, first=0, method="chebyshev",
+                   bc=BC_ZERO):
     """Values of the iterate after n sweeps (weights first .. first+n-1, cyclic) at the
     given (i, j) nodes, 1-based.  Each value is computed on its domain of dependence
     only: sweep t updates the nodes within radius*(n - t) of each point, which is all
-    the next sweep reads.  Works at any grid size in seconds."""
-    p = Plan(nx, ny, stencil, tol, M=M, h=h)
+    the next sweep reads.  Works at any grid size in seconds.  u0 is the frame
+    array for bc = BC_FRAME."""
+    p = Plan(nx, ny, stencil, tol, M=M, h=h, method=method, bc=bc)
     f = np.ascontiguousarray(f, dtype=np.float64).reshape(ny, nx)
     r = RADIUS[stencil]
     L = lib()
-    a = pad(u0, nx, ny)
+    a = _padded(u0, nx, ny, stencil, bc)
     b = a.copy()
     for t in range(1, n + 1):
         w = p.weights[(first + t - 1) % p.M]
@@ -344,6 +445,7 @@ def sampled_sweeps(f, u0, nx, ny, stencil, tol, n, points, M=None, h=None, first
         for (i, j) in points:
             L.cjo_sweep(nx, ny, p.stencil, p.h, _ptr(f), _ptr(a), _ptr(b), w,
                         i - e, i + e, j - e, j + e)
-        L.cjo_fill_ring(nx, ny, _ptr(b))
+        if bc == BC_ZERO:
+            L.cjo_fill_ring(nx, ny, _ptr(b))
         a, b = b, a
     return np.array([a[j + 1, i + 1] for (i, j) in points])

@@ -71,3 +71,54 @@ def log_uniform_shapes(n, seed, lo=64, hi=2048):
     rng = np.random.default_rng(seed)
     a = np.exp(rng.uniform(math.log(lo), math.log(hi), (n, 2)))
     return [(int(round(x)), int(round(y))) for x, y in a]
+
+
+# ------------------------------------------------------------ the paper's test problem
+# Delta u = -(x^2 + y^2) e^{xy} on the unit square with the Dirichlet data of its
+# analytic solution u = -e^{xy} (test-problem subsection of the results).  In the
+# form A u = f with A = -Delta_h: f = (x^2 + y^2) e^{xy}.  The boundary data
+# travel in a frame of width G around the interior (G = 1 for the 5- and 9-point
+# stencils, 2 for the 17-point one, whose second layer holds analytic ghost
+# values outside the square).
+
+def frame_width(stencil):
+    return 2 if stencil == 17 else 1
+
+
+def expxy_rhs(nx, ny):
+    """f = (x^2 + y^2) e^{xy} at the interior nodes, (ny, nx)."""
+    x, y = coords(nx, ny)
+    X, Y = np.meshgrid(x, y)
+    return (X * X + Y * Y) * np.exp(X * Y)
+
+
+def expxy_exact(nx, ny):
+    """u = -e^{xy} at the interior nodes, (ny, nx)."""
+    x, y = coords(nx, ny)
+    X, Y = np.meshgrid(x, y)
+    return -np.exp(X * Y)
+
+
+def expxy_frame(nx, ny, G, interior=0.0):
+    """(ny + 2G, nx + 2G) array over nodes 1-G .. n+G: -e^{xy} on the frame of
+    width G, `interior` (a scalar or an (ny, nx) array, e.g. an initial guess)
+    inside."""
+    h = spacing(nx, ny)
+    x = np.arange(1 - G, nx + G + 1) * h
+    y = np.arange(1 - G, ny + G + 1) * h
+    X, Y = np.meshgrid(x, y)
+    out = -np.exp(X * Y)
+    out[G:ny + G, G:nx + G] = interior
+    return out
+
+
+def frame_from_function(fn, nx, ny, G, interior=0.0):
+    """Like expxy_frame for any function fn(X, Y) of the node coordinates."""
+    h = spacing(nx, ny)
+    x = np.arange(1 - G, nx + G + 1) * h
+    y = np.arange(1 - G, ny + G + 1) * h
+    X, Y = np.meshgrid(x, y)
+    out = np.asarray(fn(X, Y), dtype=np.float64)
+    out = np.array(np.broadcast_to(out, X.shape))
+    out[G:ny + G, G:nx + G] = interior
+    return out

@@ -1,0 +1,154 @@
+"""Pins of the oracle's Dirichlet-frame data (reading R9) and of its Jacobi
+method (R10), against facts fixed by the mathematics:
+
+  * every stencil here is exact on polynomials of degree <= 3, so with f = -Delta p
+    and the frame taken from p the discrete solution is p itself;
+  * the frame solve equals the dense solve of the lifted system
+    A_II u_I = f - A_IB u_B, assembled here from 1D shift matrices with
+    fixed (not reflected) end values, independently of the oracle's loops;
+  * on the paper's test problem (u = -e^{xy}) the error against the analytic
+    solution falls as h^2 for the 5- and 9-point stencils and as h^4 for the
+    17-point stencil with analytic ghosts (the orders of the stencils, §2.1);
+  * a Jacobi sweep multiplies the sine mode (1, 1), the eigenvector of D^{-1}A
+    for kappa_min, by exactly 1 - kappa_min;
+  * Jacobi and Chebyshev-Jacobi reach the same (unique) discrete solution.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle import cjm
+from paper_1705_00103_amd import inputs
+
+STENCILS = (5, 9, 17)
+
+
+def _poly(X, Y):
+    # degree 3 with terms of every degree; its Laplacian is 2 x + 3 y + 6
+    return X ** 3 - 2.0 * X * Y * Y + 0.5 * Y ** 3 + X * X - 0.3 * X * Y + 2.0 * Y * Y + 0.7 * X - 1.1
+
+
+def _lap_poly(X, Y):
+    # Delta of _poly: u_xx = 6x + 2 ; u_yy = -4x + 3y + 4
+    return (6.0 * X + 2.0) + (-4.0 * X + 3.0 * Y + 4.0)
+
+
+@pytest.mark.parametrize("st", STENCILS)
+@pytest.mark.parametrize("nx,ny", [(14, 14), (17, 9)])
+def test_cubic_is_reproduced_exactly(st, nx, ny):
+    G = inputs.frame_width(st)
+    x, y = inputs.coords(nx, ny)
+    X, Y = np.meshgrid(x, y)
+    f = -_lap_poly(X, Y)
+    exact = _poly(X, Y)
+    frame_exact = inputs.frame_from_function(_poly, nx, ny, G, interior=exact)
+    # the exact polynomial has zero residual
+    assert cjm.relative_residual(st, f, frame_exact, nx, ny, bc=cjm.BC_FRAME) < 1e-13
+    frame0 = inputs.frame_from_function(_poly, nx, ny, G)
+    r = cjm.solve(f, nx, ny, st, 1e-14, u0=frame0, bc=cjm.BC_FRAME)
+    assert r["status"] in ("ok", "stagnated")
+    assert r["u"].shape == (ny + 2 * G, nx + 2 * G)
+    assert np.array_equal(r["u"][:G], frame0[:G])                 # the frame is data
+    assert np.array_equal(r["u"][:, -G:], frame0[:, -G:])
+    assert np.abs(r["u"][G:ny + G, G:nx + G] - exact).max() < 1e-11
+    # relres is measured against the lifted right-hand side: 1 at the zero interior
+    assert r["history"][0] == 1.0
+
+
+def _shift_fixed(n, d, G):
+    """(n x (n + 2G)) rows of the 1D operator (S_d u)_i = u_{i-d} + u_{i+d} over
+    nodes 1-G .. n+G, for the interior rows i = 1..n; S_0 is the identity row."""
+    rows, cols, vals = [], [], []
+    for i in range(1, n + 1):
+        ks = (i,) if d == 0 else (i - d, i + d)
+        for k in ks:
+            rows.append(i - 1)
+            cols.append(k - 1 + G)
+            vals.append(1.0)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(n, n + 2 * G))
+
+
+@pytest.mark.parametrize("st", STENCILS)
+def test_frame_solve_matches_dense_lifted_solve(st):
+    nx, ny = 11, 8
+    G = inputs.frame_width(st)
+    taps, s = cjm.taps(st)
+    h = cjm.spacing(nx, ny)
+    # Delta_h over the interior rows, all nodes of the frame array as columns:
+    # group the taps by (|di|, |dj|) and assemble c * S_|dj| (x) S_|di| per class
+    classes = {}
+    for di, dj, c in taps:
+        classes[(abs(di), abs(dj))] = c
+    full = None
+    for (ai, aj), c in classes.items():
+        term = c * sp.kron(_shift_fixed(ny, aj, G), _shift_fixed(nx, ai, G))
+        full = term if full is None else full + term
+    Afull = (-full / (s * h * h)).tocsr()          # A = -Delta_h, interior rows
+    inside = np.zeros((ny + 2 * G, nx + 2 * G), dtype=bool)
+    inside[G:ny + G, G:nx + G] = True
+    inside = inside.ravel()
+    A_II = Afull[:, inside]
+    A_IB = Afull[:, ~inside]
+    f = inputs.expxy_rhs(nx, ny)
+    frame = inputs.expxy_frame(nx, ny, G)
+    ub = frame.ravel()[~inside]
+    u_dense = spla.spsolve(A_II.tocsc(), f.ravel() - A_IB @ ub).reshape(ny, nx)
+    r = cjm.solve(f, nx, ny, st, 1e-14, u0=frame, bc=cjm.BC_FRAME)
+    got = r["u"][G:ny + G, G:nx + G]
+    assert np.abs(got - u_dense).max() <= 1e-12 * np.abs(u_dense).max()
+    # and the denominator of relres is the lifted right-hand side's norm
+    lifted = f.ravel() - A_IB @ ub
+    p = cjm.Plan(nx, ny, st, 1.0, M=1, bc=cjm.BC_FRAME)
+    got_norm = cjm.rhs_norm(p, f, cjm.pad_frame(frame, nx, ny, st))
+    assert math.isclose(got_norm, np.linalg.norm(lifted), rel_tol=1e-13)
+
+
+@pytest.mark.parametrize("st,order", [(5, 2), (9, 2), (17, 4)])
+def test_paper_problem_converges_at_the_stencil_order(st, order):
+    G = inputs.frame_width(st)
+    errs = []
+    for N in (16, 32, 64):
+        n = N - 1
+        r = cjm.solve(inputs.expxy_rhs(n, n), n, n, st, 1e-14, u0=inputs.expxy_frame(n, n, G), bc=cjm.BC_FRAME)
+        assert r["status"] in ("ok", "stagnated")
+        errs.append(np.abs(r["u"][G:n + G, G:n + G] - inputs.expxy_exact(n, n)).max())
+    slopes = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
+    assert all(abs(sl - order) < 0.15 for sl in slopes), (errs, slopes)
+
+
+@pytest.mark.parametrize("st", STENCILS)
+def test_jacobi_sweep_scales_the_lowest_mode(st):
+    nx, ny, n = 21, 13, 7
+    # the (1, 1) sine mode of this rectangle: sin(pi i / N_x) sin(pi j / N_y)
+    i = np.arange(1, nx + 1)
+    j = np.arange(1, ny + 1)
+    u0 = np.outer(np.sin(math.pi * j / (ny + 1)), np.sin(math.pi * i / (nx + 1)))
+    p = cjm.plan(nx, ny, st, 1e-6, method="jacobi")
+    assert p.weights == [1.0] * p.M
+    got = cjm.run_sweeps(np.zeros((ny, nx)), nx, ny, st, 1e-6, n, u0=u0, method="jacobi")
+    assert np.abs(got - (1.0 - p.kmin) ** n * u0).max() < 1e-14
+
+
+@pytest.mark.parametrize("kmin,tol", [(4.7e-6, 9.5e-7), (1e-3, 1e-10), (0.3, 1e-2)])
+def test_jacobi_check_interval(kmin, tol):
+    M, pred = cjm.jacobi_check(kmin, tol)
+    nj = cjm.jacobi_sweeps_needed(kmin, tol)
+    assert (1.0 - kmin) ** nj <= tol < (1.0 - kmin) ** (nj - 1)
+    assert M & (M - 1) == 0 and M <= max(1, nj // 32) and (M == 1 or 2 * M > nj // 32)
+    assert pred * M >= nj > (pred - 1) * M
+
+
+@pytest.mark.parametrize("st", STENCILS)
+def test_jacobi_and_cjm_reach_the_same_solution(st):
+    n = 23
+    G = inputs.frame_width(st)
+    f = inputs.expxy_rhs(n, n)
+    frame = inputs.expxy_frame(n, n, G)
+    rj = cjm.solve(f, n, n, st, 1e-12, u0=frame, bc=cjm.BC_FRAME, method="jacobi")
+    rc = cjm.solve(f, n, n, st, 1e-12, u0=frame, bc=cjm.BC_FRAME)
+    assert rj["status"] == "ok" and rc["status"] == "ok"
+    assert rj["sweeps"] > 5 * rc["sweeps"]
+    assert np.abs(rj["u"] - rc["u"]).max() < 1e-9
