@@ -315,6 +315,138 @@ def run_serve(args):
     print(json.dumps(out), flush=True)
 
 
+_SERIAL_SWEEP_TIMER = r"""
+import json, sys, time
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+from oracle import cjm
+n, budget = int(sys.argv[2]), float(sys.argv[3])
+out = {"threads": cjm.threads()}
+for st in (5, 9, 17):
+    G = 2 if st == 17 else 1
+    p = cjm.plan(n, n, st, 1e-6, M=16, bc=cjm.BC_FRAME)
+    f = np.ones((n, n))
+    a = cjm.pad_frame(np.zeros((n + 2 * G, n + 2 * G)), n, n, st)
+    b = a.copy()
+    k, t0 = 0, time.perf_counter()
+    while k < 2 or time.perf_counter() - t0 < budget:
+        cjm.sweep(p, f, a, b, 1.0)
+        a, b = b, a
+        k += 1
+    out[str(st)] = (time.perf_counter() - t0) / k
+print(json.dumps(out))
+"""
+
+
+def run_paper(args):
+    """The paper's own test problem (its results section): -Delta u =
+    (x^2 + y^2) e^{xy} on the unit square with the Dirichlet data of
+    u = -e^{xy}, carried in a frame around the interior (17 points: two layers,
+    the second of analytic ghosts); N = 1024 intervals per axis; the tolerance
+    on the relative residual falls as N^-2 (tol = N^-2).  Per stencil:
+    Chebyshev-Jacobi (cj) and plain Jacobi (j) solved in full on the GPU in
+    FP64, and the CPU oracle's sweep time on the same grid, serial and on all
+    host cores, times each method's sweep count (extrapolated).  The ratios
+    take the layout of the paper's Table 1.  Then the real-error runs of its
+    Fig. 4 (right): 17-point at N = 128 and 5-point at N = 2048, whole cycles
+    until the max-norm error against -e^{xy} is <= 1e-8."""
+    import subprocess
+    import numpy as np
+    import torch
+    from paper_1705_00103_amd import cj, inputs
+
+    N = args.paper_n
+    n = N - 1
+    tol = 1.0 / (N * N)
+    f = torch.from_numpy(inputs.expxy_rhs(n, n)).to("cuda")
+    table = {}
+    for st in (5, 9, 17):
+        G = inputs.frame_width(st)
+        frame = torch.from_numpy(inputs.expxy_frame(n, n, G)).to("cuda")
+        row = {}
+        for name, method in (("cj", cj.CHEBYSHEV), ("j", cj.JACOBI)):
+            p = cj.plan(n, n, st, tol, bc=cj.BC_FRAME, method=method)
+            reps = 1 if method == cj.JACOBI else 3
+            u = frame.clone()
+            cj.solve(p, f, u)                       # warm-up (allocation, graph capture)
+            times = []
+            for _ in range(reps):
+                u.copy_(frame)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = cj.solve(p, f, u)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            err = float((u[G:n + G, G:n + G].cpu() - torch.from_numpy(inputs.expxy_exact(n, n))).abs().max())
+            row[name] = {"seconds": float(np.median(times)), "sweeps": r["sweeps"], "status": r["status"],
+                         "rel_residual": r["rel_residual"], "M": p.M, "max_error_vs_exact": err}
+            print(json.dumps({"paper_progress": "%d-point %s" % (st, name), **row[name]}), flush=True)
+            p.destroy()
+        table[st] = row
+    # CPU oracle sweep times on the same grid: serial (a child process with one
+    # OpenMP thread) and on all host cores (this process)
+    root = os.path.dirname(os.path.abspath(__file__))
+    cpu = {}
+    for label, threads in (("serial", "1"), ("all_cores", None)):
+        env = dict(os.environ)
+        if threads:
+            env["OMP_NUM_THREADS"] = threads
+        outp = subprocess.run([sys.executable, "-c", _SERIAL_SWEEP_TIMER, root, str(n), str(args.paper_cpu_s)],
+                              env=env, check=True, capture_output=True, text=True).stdout
+        cpu[label] = json.loads(outp.strip().splitlines()[-1])
+    ratios = {}
+    for st in (5, 9, 17):
+        cjg, jg = table[st]["cj"], table[st]["j"]
+        t_sweep = cpu["serial"][str(st)]
+        cj_cpu, j_cpu = cjg["sweeps"] * t_sweep, jg["sweeps"] * t_sweep
+        table[st]["cpu_serial_extrapolated_s"] = {"cj": cj_cpu, "j": j_cpu, "sweep_s": t_sweep}
+        table[st]["cpu_all_cores_sweep_s"] = cpu["all_cores"][str(st)]
+        ratios[st] = {"j_GPU/j": j_cpu / jg["seconds"], "cj/j": j_cpu / cj_cpu,
+                      "cj/j_GPU": jg["seconds"] / cj_cpu, "cj_GPU/j": j_cpu / cjg["seconds"],
+                      "cj_GPU/j_GPU": jg["seconds"] / cjg["seconds"], "cj_GPU/cj": cj_cpu / cjg["seconds"],
+                      "sweeps_j/sweeps_cj": jg["sweeps"] / cjg["sweeps"]}
+    # real-error runs
+    real = []
+    for st, NN in ((17, 128), (5, 2048)):
+        m = NN - 1
+        G = inputs.frame_width(st)
+        fr = torch.from_numpy(inputs.expxy_rhs(m, m)).to("cuda")
+        u = torch.from_numpy(inputs.expxy_frame(m, m, G)).to("cuda")
+        exact = torch.from_numpy(inputs.expxy_exact(m, m)).to("cuda")
+        p = cj.plan(m, m, st, 1e-12, bc=cj.BC_FRAME)
+        hist, sweeps, secs = [], 0, 0.0
+        while True:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            cj.sweeps(p, fr, u, p.M)
+            torch.cuda.synchronize()
+            secs += time.perf_counter() - t0
+            sweeps += p.M
+            e = float((u[G:m + G, G:m + G] - exact).abs().max())
+            hist.append([sweeps, e])
+            if e <= 1e-8 or len(hist) >= 64:
+                break
+        real.append({"stencil": st, "N": NN, "M": p.M, "sweeps": sweeps, "seconds": secs,
+                     "final_error": hist[-1][1], "reached_1e-8": hist[-1][1] <= 1e-8, "history": hist})
+        p.destroy()
+    out = {
+        "metric": "time-to-tolerance ratio, Jacobi over Chebyshev-Jacobi, both on the GPU (5-point)",
+        "value": ratios[5]["cj_GPU/j_GPU"],
+        "unit": "x",
+        "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": table[5]["cj"]["seconds"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic (analytic test problem)",
+        "config": {"workload": "paper-test-problem-expxy-N%d-tolN^-2" % N, "N": N, "tol": tol,
+                   "parallelism": "single-gpu"},
+        "table1": {str(k): v for k, v in table.items()},
+        "table1_ratios": {str(k): v for k, v in ratios.items()},
+        "cpu_oracle_threads": {"serial": cpu["serial"]["threads"], "all_cores": cpu["all_cores"]["threads"]},
+        "real_error_runs": real,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -333,7 +465,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run only the short copy + sweep probe used for rocprofv3 counter passes")
-    ap.add_argument("--workload", choices=("single", "batch", "serve"), default="single",
+    ap.add_argument("--workload", choices=("single", "batch", "serve", "paper"), default="single",
                     help="single: one large solve (default); batch: many uneven problems in shared launches; "
                          "serve: Poisson arrivals into the continuous-batching server")
     ap.add_argument("--serve-n", type=int, default=160, help="serve: number of requests")
@@ -341,6 +473,8 @@ def main():
     ap.add_argument("--serve-lo", type=int, default=64)
     ap.add_argument("--serve-hi", type=int, default=4096)
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
+    ap.add_argument("--paper-n", type=int, default=1024, help="paper: intervals per axis")
+    ap.add_argument("--paper-cpu-s", type=float, default=1.0, help="paper: CPU sweep-timing budget per stencil")
     ap.add_argument("--batch-n", type=int, default=512)
     ap.add_argument("--batch-lo", type=int, default=64)
     ap.add_argument("--batch-hi", type=int, default=2048)
@@ -366,6 +500,9 @@ def main():
         return
     if args.workload == "serve":
         run_serve(args)
+        return
+    if args.workload == "paper":
+        run_paper(args)
         return
     n, st, tol = args.n, args.stencil, args.tol
     ny = args.n if args.ny is None else args.ny

@@ -14,17 +14,30 @@
  * Problem.  nx x ny interior unknowns u(i, j), 1 <= i <= nx, 1 <= j <= ny, at
  * x_i = i h, y_j = j h on a uniform mesh.  The paper's N_x, N_y (number of
  * intervals) are nx + 1 and ny + 1; the default mesh spacing is
- * h = 1 / max(nx + 1, ny + 1).  Homogeneous Dirichlet data on the boundary
- * nodes i in {0, nx + 1}, j in {0, ny + 1}.  The system solved is A u = f
+ * h = 1 / max(nx + 1, ny + 1).  Dirichlet data on the boundary nodes
+ * i in {0, nx + 1}, j in {0, ny + 1}.  The system solved is A u = f
  * with A = -Delta_h, Delta_h the chosen stencil (§2.1, Eq. "9-points" and
  * Eq. "17-points"; Table "tab:ste2" for the classical 5-point stencil).  The
- * 17-point stencil reaches one node beyond the boundary; that node holds the
- * odd reflection of the interior (u(-1, j) = -u(1, j), likewise on every
- * side), which keeps the sine modes exact eigenvectors.
+ * 17-point stencil reaches one node beyond the boundary.
  *
- * Arrays.  f and u are device pointers to nx*ny doubles, row-major with x
- * fastest: element (i, j) at index (j - 1) * nx + (i - 1).  They must be
- * 8-byte aligned.  The caller owns them; the library never frees them.
+ * Boundary data (cj_bc).
+ *   CJ_BC_DIRICHLET0: homogeneous data; the node beyond the boundary holds the
+ *     odd reflection of the interior (u(-1, j) = -u(1, j), likewise on every
+ *     side), which keeps the sine modes exact eigenvectors.
+ *   CJ_BC_DIRICHLET_FRAME: arbitrary data carried by u itself, as in the
+ *     paper's test problem (§3, boundaries from the analytic solution): u is
+ *     the (nx + 2G) x (ny + 2G) array over nodes 1-G .. n+G with the interior
+ *     inside a frame of width G = 1 (5-, 9-point) or G = 2 (17-point, whose
+ *     second layer holds prescribed ghost values).  The frame is read, never
+ *     written.  The relative residual is measured against the residual of the
+ *     zero interior, i.e. the norm of the lifted right-hand side
+ *     f - A_IB u_B.
+ *
+ * Arrays.  f is a device pointer to nx*ny doubles, row-major with x fastest:
+ * element (i, j) at index (j - 1) * nx + (i - 1).  u has the same layout
+ * (CJ_BC_DIRICHLET0) or the frame layout above, element (i, j) at index
+ * (j - 1 + G) * (nx + 2G) + (i - 1 + G).  Arrays must be 8-byte aligned.  The
+ * caller owns them; the library never frees them.
  *
  * Streams.  `stream` is a hipStream_t passed as void* (NULL = the null
  * stream).  All device work of a call is enqueued on that stream.  cj_solve,
@@ -59,7 +72,16 @@ typedef enum {
 
 typedef enum { CJ_STENCIL_5 = 5, CJ_STENCIL_9 = 9, CJ_STENCIL_17 = 17 } cj_stencil;
 
-typedef enum { CJ_BC_DIRICHLET0 = 0 } cj_bc;
+typedef enum { CJ_BC_DIRICHLET0 = 0, CJ_BC_DIRICHLET_FRAME = 1 } cj_bc;
+
+/* Iteration (cj_options.method).
+ * CJ_METHOD_CHEBYSHEV: the Chebyshev-Jacobi method (§2.1).
+ * CJ_METHOD_JACOBI: plain Jacobi, omega = 1 (the paper's reference method,
+ *   §3).  M is then the interval between residual tests: 0 selects the
+ *   largest power of two not above n_J / 32, where n_J sweeps meet tol under
+ *   the bound (1 - kappa_min)^n; the predicted cycle count is ceil(n_J / M).
+ *   FP64 only. */
+typedef enum { CJ_METHOD_CHEBYSHEV = 0, CJ_METHOD_JACOBI = 1 } cj_method;
 
 /* Working precision of a plan.
  * CJ_PRECISION_F64: FP64 sweeps, the method as stated (§2.1).
@@ -91,7 +113,8 @@ typedef struct {
     int    graph;              /* FP64 solves: replay each cycle's plain launches as one HIP
                                   graph; 0 = automatic (grids of at most 2^22 points, where
                                   launch overhead matters), 1 = always, -1 = never */
-    int    reserved[5];        /* must be zero */
+    int    method;             /* cj_method; 0 = CJ_METHOD_CHEBYSHEV */
+    int    reserved[4];        /* must be zero */
 } cj_options;
 
 /* Outcome of a solve. */
@@ -117,7 +140,8 @@ void cj_options_init(cj_options* opt);
  * theta_j running over the odd integers 1 .. 2M - 1 in the recursive
  * symmetric-pair order S_1 = [1], S_2m = [s_1, 4m - s_1, s_2, 4m - s_2, ...]
  * (keeps every tail product of the cycle polynomial bounded by one).
- * nx, ny >= 1; stencil in {5, 9, 17}; bc = CJ_BC_DIRICHLET0; tol > 0.
+ * nx, ny >= 1; stencil in {5, 9, 17}; bc a cj_bc (CJ_BC_DIRICHLET_FRAME
+ * with CJ_PRECISION_F64 or CJ_PRECISION_F32_REFINE); tol > 0.
  * On success *out owns the plan; release it with cj_plan_destroy. */
 cj_status cj_plan(int nx, int ny, int stencil, int bc, double tol, cj_plan_t* out);
 cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol,
@@ -139,8 +163,9 @@ cj_status cj_plan_info(cj_plan_t p, double* kmin, double* kmax, int* M, int* cyc
 cj_status cj_plan_launch_info(cj_plan_t p, int* sweeps_per_launch, int* tile_rows, int* workgroups);
 
 /* Solves A u = f.  u is read as the initial guess and overwritten with the
- * solution.  Cycles of M sweeps are run; the relative residual
- * ||f - A u||_2 / ||f||_2 is tested at cycle ends only (the paper stops at a
+ * solution (CJ_BC_DIRICHLET_FRAME: its interior; the frame is the data).
+ * Cycles of M sweeps are run; the relative residual ||f - A u||_2 / ||f||_2
+ * (frame: over the lifted right-hand side) is tested at cycle ends only (the paper stops at a
  * prescribed tolerance, §3.4; mid-cycle iterates are not meaningful).  Stops
  * with CJ_OK when it is <= tol; with CJ_STAGNATED when, at or after the
  * predicted cycle count, a cycle fails to halve it (the FP64 floor of large
@@ -158,12 +183,14 @@ cj_status cj_solve(cj_plan_t p, const double* f, double* u, void* stream, cj_res
  * FP32, the sweeps run in FP32 and the result is widened back. */
 cj_status cj_sweeps(cj_plan_t p, const double* f, double* u, long long n_sweeps, void* stream);
 
-/* *rel_residual = ||f - A u||_2 / ||f||_2 (0 when f = 0), FP64 with a
- * deterministic reduction order. */
+/* *rel_residual = ||f - A u||_2 / ||f||_2 (0 when f = 0; frame: over the
+ * lifted right-hand side), FP64 with a deterministic reduction order. */
 cj_status cj_residual(cj_plan_t p, const double* f, const double* u, void* stream,
                       double* rel_residual);
 
-/* au = A u = -Delta_h u (the stencil apply), same layout as u. */
+/* au = A u = -Delta_h u (the stencil apply) on the interior; au has the
+ * nx*ny layout of f.  With CJ_BC_DIRICHLET_FRAME the frame values enter the
+ * stencil as they stand. */
 cj_status cj_apply(cj_plan_t p, const double* u, double* au, void* stream);
 
 /* ------------------------------------------------------------------ batches

@@ -330,10 +330,11 @@ def residual_sumsq(p, f, u_pad):
     return lib().cjo_residual_sumsq(p.nx, p.ny, p.stencil, p.h, _ptr(f), _ptr(u_pad))
 
 
-def apply(stencil, u, nx, ny, h=None):
-    """A u = -Delta_h u for an unpadded (ny, nx) array."""
+def apply(stencil, u, nx, ny, h=None, bc=BC_ZERO):
+    """A u = -Delta_h u on the interior, (ny, nx); u is (ny, nx), or the frame
+    array for bc = BC_FRAME (its frame values enter the stencil)."""
     h = spacing(nx, ny) if h is None else h
-    up = pad(u, nx, ny)
+    up = _padded(u, nx, ny, stencil, bc)
     out = np.empty((ny, nx), dtype=np.float64)
     if lib().cjo_apply(nx, ny, stencil, h, _ptr(up), _ptr(out)) != 0:
         raise ValueError("unknown stencil")

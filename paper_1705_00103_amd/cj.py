@@ -9,6 +9,9 @@ device memory and the current HIP stream; nothing else.
     p = cj.plan(nx, ny, stencil=9, tol=1e-10)
     u = torch.zeros(ny, nx, dtype=torch.float64, device="cuda")
     res = cj.solve(p, f, u)        # u now holds the solution
+
+With bc=BC_FRAME, u is (ny + 2G, nx + 2G) and carries the Dirichlet data in
+its frame of width G = plan.frame (1, or 2 for the 17-point stencil).
 """
 import ctypes
 import os
@@ -27,6 +30,10 @@ CJ_ERR_DEVICE = -6
 
 F64 = 0             # CJ_PRECISION_F64
 F32_REFINE = 1      # CJ_PRECISION_F32_REFINE
+BC_ZERO = 0         # CJ_BC_DIRICHLET0
+BC_FRAME = 1        # CJ_BC_DIRICHLET_FRAME: u carries the boundary data in a frame
+CHEBYSHEV = 0       # CJ_METHOD_CHEBYSHEV
+JACOBI = 1          # CJ_METHOD_JACOBI
 
 STATUS_NAMES = {
     CJ_OK: "ok", CJ_STAGNATED: "stagnated", CJ_ERR_ARG: "arg", CJ_ERR_NOMEM: "nomem",
@@ -45,7 +52,7 @@ class Options(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int), ("max_cycles", ctypes.c_int),
                 ("sweeps_per_launch", ctypes.c_int), ("tile_rows", ctypes.c_int),
                 ("h", ctypes.c_double), ("precision", ctypes.c_int), ("inner_M", ctypes.c_int),
-                ("graph", ctypes.c_int), ("reserved", ctypes.c_int * 5)]
+                ("graph", ctypes.c_int), ("method", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
 
 
 class Result(ctypes.Structure):
@@ -155,13 +162,15 @@ class Plan:
     """Owns a cj_plan_t.  Attributes mirror cj_plan_info."""
 
     def __init__(self, nx, ny, stencil=9, tol=1e-10, M=0, max_cycles=0, sweeps_per_launch=0,
-                 tile_rows=0, h=0.0, bc=0, precision=F64, inner_M=0, graph=0):
+                 tile_rows=0, h=0.0, bc=BC_ZERO, precision=F64, inner_M=0, graph=0, method=CHEBYSHEV):
         L = lib()
         o = Options()
         L.cj_options_init(ctypes.byref(o))
         o.M, o.max_cycles, o.sweeps_per_launch, o.tile_rows, o.h = M, max_cycles, sweeps_per_launch, tile_rows, h
-        o.precision, o.inner_M, o.graph = precision, inner_M, graph
-        self.precision = precision
+        o.precision, o.inner_M, o.graph, o.method = precision, inner_M, graph, method
+        self.precision, self.bc, self.method = precision, bc, method
+        # width of u's boundary frame (CJ_BC_DIRICHLET_FRAME)
+        self.frame = (2 if stencil == 17 else 1) if bc == BC_FRAME else 0
         handle = ctypes.c_void_p()
         _check(L.cj_plan_ex(nx, ny, stencil, bc, tol, ctypes.byref(o), ctypes.byref(handle)), "cj_plan_ex")
         self._h = handle
@@ -202,14 +211,17 @@ def plan(nx, ny, stencil=9, tol=1e-10, **opts):
     return Plan(nx, ny, stencil, tol, **opts)
 
 
-def _grid_ptr(t, p, name, writable=False):
+def _grid_ptr(t, p, name, framed=False):
+    """framed: the array is u of a CJ_BC_DIRICHLET_FRAME plan, (ny + 2G) x (nx + 2G)."""
     import torch
     if not isinstance(t, torch.Tensor):
         raise TypeError("%s must be a torch tensor" % name)
     if t.device.type != "cuda" or t.dtype != torch.float64 or not t.is_contiguous():
         raise ValueError("%s must be a contiguous float64 GPU tensor" % name)
-    if t.numel() != p.nx * p.ny:
-        raise ValueError("%s has %d elements, the plan needs nx*ny = %d" % (name, t.numel(), p.nx * p.ny))
+    G = p.frame if framed else 0
+    need = (p.nx + 2 * G) * (p.ny + 2 * G)
+    if t.numel() != need:
+        raise ValueError("%s has %d elements, the plan needs %d" % (name, t.numel(), need))
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -224,7 +236,8 @@ def solve(p, f, u, stream=None, raise_on_error=False):
     status 'stagnated' and 'not_converged' are results, not exceptions, unless
     raise_on_error is set.  Argument and runtime errors raise CJError."""
     r = Result()
-    code = lib().cj_solve(p.handle, _grid_ptr(f, p, "f"), _grid_ptr(u, p, "u"), _stream(stream), ctypes.byref(r))
+    code = lib().cj_solve(p.handle, _grid_ptr(f, p, "f"), _grid_ptr(u, p, "u", True), _stream(stream),
+                          ctypes.byref(r))
     if code in (CJ_ERR_ARG, CJ_ERR_NOMEM, CJ_ERR_HIP, CJ_ERR_DEVICE) or (raise_on_error and code != CJ_OK):
         raise CJError(code, "cj_solve", last_error())
     return r.as_dict()
@@ -232,21 +245,22 @@ def solve(p, f, u, stream=None, raise_on_error=False):
 
 def sweeps(p, f, u, n, stream=None):
     """Applies the first n sweeps of the plan's schedule to u in place."""
-    _check(lib().cj_sweeps(p.handle, _grid_ptr(f, p, "f"), _grid_ptr(u, p, "u"), int(n), _stream(stream)),
+    _check(lib().cj_sweeps(p.handle, _grid_ptr(f, p, "f"), _grid_ptr(u, p, "u", True), int(n), _stream(stream)),
            "cj_sweeps")
 
 
 def residual(p, f, u, stream=None):
     """||f - A u|| / ||f||."""
     out = ctypes.c_double()
-    _check(lib().cj_residual(p.handle, _grid_ptr(f, p, "f"), _grid_ptr(u, p, "u"), _stream(stream),
+    _check(lib().cj_residual(p.handle, _grid_ptr(f, p, "f"), _grid_ptr(u, p, "u", True), _stream(stream),
                              ctypes.byref(out)), "cj_residual")
     return out.value
 
 
 def apply(p, u, au, stream=None):
     """au = A u."""
-    _check(lib().cj_apply(p.handle, _grid_ptr(u, p, "u"), _grid_ptr(au, p, "au"), _stream(stream)), "cj_apply")
+    _check(lib().cj_apply(p.handle, _grid_ptr(u, p, "u", True), _grid_ptr(au, p, "au"), _stream(stream)),
+           "cj_apply")
 
 
 class Batch:

@@ -25,14 +25,22 @@ struct Schedule {
 bool make_schedule(int stencil, int nx, int ny, double tol, double h, int M_request,
                    Schedule* s, std::string* err);
 
+// Plain Jacobi: all weights 1, M = the interval between residual checks
+// (0: automatic), cycles_pred = the predicted number of checks.
+bool make_jacobi_schedule(int stencil, int nx, int ny, double tol, double h, int M_request,
+                          Schedule* s, std::string* err);
+
 // ---------------------------------------------------------------- device layout
 
 // Padded, pitched storage of a grid function: node (x, y) for
 // -1 <= x <= nx + 2, -1 <= y <= ny + 2 lives at (y + 1) * pitch + (x + xoff),
 // xoff = 128 / element_bytes - 1, which puts the first interior column x = 1
 // on a 128-byte boundary.  The ring x in {0, nx+1}, y in {0, ny+1} holds the
-// Dirichlet zeros; the outer ring x in {-1, nx+2}, y in {-1, ny+2} holds the
-// odd reflection of the interior (read by the 17-point stencil only).
+// Dirichlet data; the outer ring x in {-1, nx+2}, y in {-1, ny+2} is read by
+// the 17-point stencil only.  frame = 0 (homogeneous data): the ring holds
+// zeros and the outer ring the odd reflection of the interior.  frame = G > 0:
+// the caller's u carries the boundary data in a frame of width G (1: 5/9-point,
+// 2: 17-point) and both rings hold data that no sweep changes.
 __host__ __device__ constexpr int xoff_of(int elem_bytes) { return 128 / elem_bytes - 1; }
 
 struct Layout {
@@ -40,9 +48,10 @@ struct Layout {
     int elem_bytes = 8;
     int pitch = 0;          // elements per stored row
     size_t elems = 0;       // elements per padded array
+    int frame = 0;          // width of the caller's boundary frame (0: homogeneous data)
 };
 
-Layout make_layout(int nx, int ny, int elem_bytes);
+Layout make_layout(int nx, int ny, int elem_bytes, int frame = 0);
 
 // Launch geometry of the tile kernels (sweeps, residual, stage-in).
 struct Tiles {
@@ -89,17 +98,19 @@ struct BatchItem {
 // ---------------------------------------------------------------- launchers
 // Every launcher enqueues on `stream` and returns the launch status.
 
-// Interior of A and B <- u (user layout), interior of G <- scale * f; per-tile
-// partial sums of G^2 into part[0 .. tiles.count()).
+// Interior of A <- u (user layout; with L.frame > 0 the interior of u's frame
+// layout), of B <- u (L.frame > 0: zero), of G <- scale * f (f == nullptr:
+// zero); per-tile partial sums of G^2 into part[0 .. tiles.count()).
 hipError_t launch_stage_in(const Layout& L, const Tiles& T, const double* f, const double* u,
                            double scale, double* A, double* B, double* G, double* part,
                            hipStream_t stream);
 
-// Ring of A, B (reflection of u) and G (zeros).
+// Ring of A, B (L.frame = 0: zeros and the reflection of u; else the frame
+// values of u) and of G (zeros).
 hipError_t launch_ring(const Layout& L, const double* u, double* A, double* B, double* G,
                        hipStream_t stream);
 
-// u (user layout) <- interior of A.
+// u (user layout; L.frame > 0: the interior of the frame layout) <- interior of A.
 hipError_t launch_stage_out(const Layout& L, const double* A, double* u, hipStream_t stream);
 
 // One weighted sweep uout <- uin + w[widx] * r(uin), r = g - D^{-1} A uin in

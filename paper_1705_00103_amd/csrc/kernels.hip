@@ -112,12 +112,14 @@ __device__ __forceinline__ double block_sum(double v) {
 }
 
 // Stores u'(x, y) with a streaming (non-temporal) store: the new iterate is not
-// read again before it has left the caches.  For the 17-point stencil the odd
-// reflections on the outer ring are kept up to date as well.
-template <typename T, int ST>
+// read again before it has left the caches.  REFL (17-point stencil with
+// homogeneous data): the odd reflections on the outer ring are kept up to date
+// as well.  Without it every node outside the interior holds data that the
+// sweeps never change.
+template <typename T, int ST, bool REFL>
 __device__ __forceinline__ void store_update(T* __restrict__ uout, int pitch, int nx, int ny, int x, int y, T un) {
     __builtin_nontemporal_store(un, uout + at<T>(pitch, x, y));
-    if (ST == 17) {
+    if (ST == 17 && REFL) {
         if (x == 1) uout[at<T>(pitch, -1, y)] = -un;
         if (x == nx) uout[at<T>(pitch, nx + 2, y)] = -un;
         if (y == 1) {
@@ -139,7 +141,7 @@ __device__ __forceinline__ void store_update(T* __restrict__ uout, int pitch, in
 // (2R+1 columns) per output row.  WRITE: store the update; NORM: accumulate
 // r^2 of the input iterate (FP64 only).
 
-template <typename T, int ST, bool WRITE, bool NORM>
+template <typename T, int ST, bool WRITE, bool NORM, bool REFL>
 __global__ __launch_bounds__(256) void sweep_kernel(const T* __restrict__ uin, T* __restrict__ uout,
                                                     const T* __restrict__ g, const T* __restrict__ w, int widx,
                                                     int nx, int ny, int pitch, int tiles_x, int rows,
@@ -176,7 +178,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(const T* __restrict__ uin, T
         const T uc = v[R][R];
         const T res = (gv + neighbour_sum<T, ST>(v)) - uc;
         if (NORM) acc = fmat<double>((double)res, (double)res, acc);
-        if (WRITE && active) store_update<T, ST>(uout, pitch, nx, ny, x, y, fmat<T>(omega, res, uc));
+        if (WRITE && active) store_update<T, ST, REFL>(uout, pitch, nx, ny, x, y, fmat<T>(omega, res, uc));
     }
     if (NORM) {
         if (!active) acc = 0.0;
@@ -201,8 +203,11 @@ __global__ __launch_bounds__(256) void sweep_kernel(const T* __restrict__ uin, T
 // (256 - 2KR output columns) and the tiles overlap in y by KR rows.
 // The row loop is unrolled by the window height W = 2R+1 so that the window
 // rotation is a compile-time renaming of registers.  Workgroups whose halo
-// reaches the domain boundary take a variant that closes the levels >= 1 with
-// the Dirichlet zeros and the odd reflections; interior workgroups skip it.
+// reaches the domain boundary take a variant that closes the levels >= 1:
+// with REFL (17-point, homogeneous data) by the Dirichlet zeros and the odd
+// reflections of the level below; otherwise every node outside the interior
+// keeps, at every level, the value level 0 loaded for it (the boundary data).
+// Interior workgroups skip both.
 // Every update evaluates exactly the expression of sweep_kernel on exactly the
 // same values, so K sweeps here give the same bits as K launches of it.
 
@@ -211,37 +216,43 @@ struct March {
     static constexpr int R = Stencil<ST>::R;
     static constexpr int W = 2 * R + 1;
     static constexpr int WOUT = 256 - 2 * K * R;
+    // level-0 rows are fetched PD row steps ahead: W steps for the 3-row
+    // window (a step is shorter than the HBM latency under load), one step for
+    // the 5-row window (its registers are spent on the wider window)
+    static constexpr int PD = (R == 1) ? W : 1;
     T win[K][W][W];   // [level][physical row slot][column x-R .. x+R]
     T gw[K][W];       // g of the lane's column on each window row
     T own[K];         // the lane's value of the row a level produced in this step
     T gused[K];       // the g it used
-    T pre[W];         // prefetched level-0 row
-    T pg;             // and its g
+    T pre[PD][W];     // prefetched level-0 rows
+    T pg[PD];         // and their g
     int lcol[W];      // level-0 load columns (clamped), with the layout offset
     int xsrc[W];      // exchange source lanes for the x +- R neighbours
-    int xsgn[W];      // 1, 0 (Dirichlet column) or -1 (reflection), edge workgroups only
+    int xsgn[W];      // 1, 0 (Dirichlet column) or -1 (reflection), REFL edge workgroups only
 };
 
 // One row step with compile-time phase J = t mod W.  Level 0 enters slot J at
 // the start of the step; level s >= 1 enters slot J at its end.
-template <typename T, int ST, int K, bool NORM, bool EDGE, int J>
+template <typename T, int ST, int K, bool NORM, bool REFL, bool EDGE, int J>
 __device__ __forceinline__ void march_step(March<T, ST, K>& S, T (*xch)[March<T, ST, K>::W][256],
                                            const T* __restrict__ uin, T* __restrict__ uout, const T* __restrict__ g,
                                            const T (&om)[K], int t, int ybase, int x, int xg, bool out_col, int Y0,
                                            int Y1, int nx, int ny, int pitch, double& acc) {
     constexpr int R = Stencil<ST>::R;
     constexpr int W = 2 * R + 1;
+    constexpr int PD = March<T, ST, K>::PD;
+    constexpr int P = J % PD;     // prefetch slot of this phase
     const int tid = threadIdx.x;
     const int yl = ybase + t;
 #pragma unroll
-    for (int c = 0; c < W; ++c) S.win[0][J][c] = S.pre[c];
-    S.gw[0][J] = S.pg;
-    {   // prefetch the next level-0 row and its g
-        const int yr = min(max(yl + 1, -1), ny + 2);
+    for (int c = 0; c < W; ++c) S.win[0][J][c] = S.pre[P][c];
+    S.gw[0][J] = S.pg[P];
+    {   // prefetch the level-0 row PD steps ahead, and its g
+        const int yr = min(max(yl + PD, -1), ny + 2);
         const T* rowp = uin + (size_t)(yr + 1) * (size_t)pitch;
 #pragma unroll
-        for (int c = 0; c < W; ++c) S.pre[c] = rowp[S.lcol[c]];
-        S.pg = __builtin_nontemporal_load(g + at<T>(pitch, xg, yr));
+        for (int c = 0; c < W; ++c) S.pre[P][c] = rowp[S.lcol[c]];
+        S.pg[P] = __builtin_nontemporal_load(g + at<T>(pitch, xg, yr));
     }
 #pragma unroll
     for (int s = 1; s <= K; ++s) {
@@ -257,7 +268,7 @@ __device__ __forceinline__ void march_step(March<T, ST, K>& S, T (*xch)[March<T,
             for (int c = 0; c < W; ++c) v[r][c] = S.win[s - 1][ph][c];
             if (r == R) gv = S.gw[s - 1][ph];
         }
-        if (EDGE && s > 1 && (Y - R < 1 || Y + R > ny)) {
+        if (REFL && EDGE && s > 1 && (Y - R < 1 || Y + R > ny)) {
             // rows beyond the interior: Dirichlet zeros, second ring by odd reflection
 #pragma unroll
             for (int r = 0; r < W; ++r) {
@@ -276,14 +287,16 @@ __device__ __forceinline__ void march_step(March<T, ST, K>& S, T (*xch)[March<T,
         }
         const T uc = v[R][R];
         const T res = (gv + neighbour_sum<T, ST>(v)) - uc;
-        const T un = fmat<T>(om[s - 1], res, uc);
+        T un = fmat<T>(om[s - 1], res, uc);
+        // boundary data: a node outside the interior keeps its value
+        if (!REFL && EDGE && (x < 1 || x > nx || Y < 1 || Y > ny)) un = uc;
         if (NORM && s == 1 && out_col && Y >= Y0 && Y < Y1) acc = fmat<double>((double)res, (double)res, acc);
         if (s < K) {
             xch[s - 1][J][tid] = un;
             S.own[s] = un;
             S.gused[s] = gv;
         } else if (out_col && Y >= Y0 && Y < Y1) {
-            store_update<T, ST>(uout, pitch, nx, ny, x, Y, un);
+            store_update<T, ST, REFL>(uout, pitch, nx, ny, x, Y, un);
         }
     }
     if (K > 1) {
@@ -297,7 +310,7 @@ __device__ __forceinline__ void march_step(March<T, ST, K>& S, T (*xch)[March<T,
                     val = S.own[s];
                 } else {
                     const T e = xch[s - 1][J][S.xsrc[c]];
-                    if (EDGE)
+                    if (REFL && EDGE)
                         val = S.xsgn[c] == 0 ? T(0) : (S.xsgn[c] < 0 ? -e : e);
                     else
                         val = e;
@@ -309,30 +322,30 @@ __device__ __forceinline__ void march_step(March<T, ST, K>& S, T (*xch)[March<T,
     }
 }
 
-template <typename T, int ST, int K, bool NORM, bool EDGE>
+template <typename T, int ST, int K, bool NORM, bool REFL, bool EDGE>
 __device__ __forceinline__ void march(March<T, ST, K>& S, T (*xch)[March<T, ST, K>::W][256],
                                       const T* __restrict__ uin, T* __restrict__ uout, const T* __restrict__ g,
                                       const T (&om)[K], int ybase, int steps, int x, int xg, bool out_col, int Y0,
                                       int Y1, int nx, int ny, int pitch, double& acc) {
     constexpr int W = March<T, ST, K>::W;
     for (int t = 0; t < steps; t += W) {
-        march_step<T, ST, K, NORM, EDGE, 0>(S, xch, uin, uout, g, om, t, ybase, x, xg, out_col, Y0, Y1, nx, ny,
+        march_step<T, ST, K, NORM, REFL, EDGE, 0>(S, xch, uin, uout, g, om, t, ybase, x, xg, out_col, Y0, Y1, nx, ny,
                                             pitch, acc);
-        march_step<T, ST, K, NORM, EDGE, 1>(S, xch, uin, uout, g, om, t + 1, ybase, x, xg, out_col, Y0, Y1, nx,
+        march_step<T, ST, K, NORM, REFL, EDGE, 1>(S, xch, uin, uout, g, om, t + 1, ybase, x, xg, out_col, Y0, Y1, nx,
                                             ny, pitch, acc);
-        march_step<T, ST, K, NORM, EDGE, 2>(S, xch, uin, uout, g, om, t + 2, ybase, x, xg, out_col, Y0, Y1, nx,
+        march_step<T, ST, K, NORM, REFL, EDGE, 2>(S, xch, uin, uout, g, om, t + 2, ybase, x, xg, out_col, Y0, Y1, nx,
                                             ny, pitch, acc);
         if constexpr (W == 5) {
-            march_step<T, ST, K, NORM, EDGE, 3>(S, xch, uin, uout, g, om, t + 3, ybase, x, xg, out_col, Y0, Y1,
+            march_step<T, ST, K, NORM, REFL, EDGE, 3>(S, xch, uin, uout, g, om, t + 3, ybase, x, xg, out_col, Y0, Y1,
                                                 nx, ny, pitch, acc);
-            march_step<T, ST, K, NORM, EDGE, 4>(S, xch, uin, uout, g, om, t + 4, ybase, x, xg, out_col, Y0, Y1,
+            march_step<T, ST, K, NORM, REFL, EDGE, 4>(S, xch, uin, uout, g, om, t + 4, ybase, x, xg, out_col, Y0, Y1,
                                                 nx, ny, pitch, acc);
         }
     }
 }
 
 // The blocked sweeps of one tile (strip sx, row tile sy = tile / strips_x).
-template <typename T, int ST, int K, bool NORM>
+template <typename T, int ST, int K, bool NORM, bool REFL>
 __device__ __forceinline__ void sweepk_tile(const T* __restrict__ uin, T* __restrict__ uout, const T* __restrict__ g,
                                             const T* __restrict__ w, int widx, int nx, int ny, int pitch,
                                             int strips_x, int rows, int tile, double* __restrict__ part) {
@@ -359,9 +372,11 @@ __device__ __forceinline__ void sweepk_tile(const T* __restrict__ uin, T* __rest
         S.lcol[c] = min(max(x - R + c, -1), nx + 2) + xoff_of(sizeof(T));
         const int dx = c - R, col = x + dx;
         int idx = tid + dx, sg = 1;
-        if (col == 0 || col == nx + 1) sg = 0;
-        else if (col == -1) { idx = tid + dx + 2; sg = -1; }
-        else if (col == nx + 2) { idx = tid + dx - 2; sg = -1; }
+        if (REFL) {
+            if (col == 0 || col == nx + 1) sg = 0;
+            else if (col == -1) { idx = tid + dx + 2; sg = -1; }
+            else if (col == nx + 2) { idx = tid + dx - 2; sg = -1; }
+        }
         S.xsrc[c] = min(max(idx, 0), 255);
         S.xsgn[c] = sg;
     }
@@ -378,20 +393,21 @@ __device__ __forceinline__ void sweepk_tile(const T* __restrict__ uin, T* __rest
         }
     }
     const int ybase = Y0 - K * R;   // level-0 row entering at step 0
-    {
-        const int yr = min(max(ybase, -1), ny + 2);
+#pragma unroll
+    for (int q = 0; q < MS::PD; ++q) {
+        const int yr = min(max(ybase + q, -1), ny + 2);
         const T* rowp = uin + (size_t)(yr + 1) * (size_t)pitch;
 #pragma unroll
-        for (int c = 0; c < W; ++c) S.pre[c] = rowp[S.lcol[c]];
-        S.pg = __builtin_nontemporal_load(g + at<T>(pitch, xg, yr));
+        for (int c = 0; c < W; ++c) S.pre[q][c] = rowp[S.lcol[c]];
+        S.pg[q] = __builtin_nontemporal_load(g + at<T>(pitch, xg, yr));
     }
     double acc = 0.0;
     const int steps = (Y1 - Y0) + 2 * K * R + K - 1;
     if (edge)
-        march<T, ST, K, NORM, true>(S, xch, uin, uout, g, om, ybase, steps, x, xg, out_col, Y0, Y1, nx, ny, pitch,
+        march<T, ST, K, NORM, REFL, true>(S, xch, uin, uout, g, om, ybase, steps, x, xg, out_col, Y0, Y1, nx, ny, pitch,
                                     acc);
     else
-        march<T, ST, K, NORM, false>(S, xch, uin, uout, g, om, ybase, steps, x, xg, out_col, Y0, Y1, nx, ny, pitch,
+        march<T, ST, K, NORM, REFL, false>(S, xch, uin, uout, g, om, ybase, steps, x, xg, out_col, Y0, Y1, nx, ny, pitch,
                                      acc);
     if (NORM) {
         const double tot = block_sum(acc);
@@ -399,12 +415,12 @@ __device__ __forceinline__ void sweepk_tile(const T* __restrict__ uin, T* __rest
     }
 }
 
-template <typename T, int ST, int K, bool NORM>
+template <typename T, int ST, int K, bool NORM, bool REFL>
 __global__ __launch_bounds__(256) void sweepk_kernel(const T* __restrict__ uin, T* __restrict__ uout,
                                                      const T* __restrict__ g, const T* __restrict__ w, int widx,
                                                      int nx, int ny, int pitch, int strips_x, int rows,
                                                      double* __restrict__ part) {
-    sweepk_tile<T, ST, K, NORM>(uin, uout, g, w, widx, nx, ny, pitch, strips_x, rows,
+    sweepk_tile<T, ST, K, NORM, REFL>(uin, uout, g, w, widx, nx, ny, pitch, strips_x, rows,
                                 xcd_tile(blockIdx.x, gridDim.x), part);
 }
 
@@ -424,7 +440,7 @@ __global__ __launch_bounds__(256) void batch_sweepk_kernel(const BatchProblem* _
     const int j = step - pb.cycle_start;
     const float* uin = (j & 1) ? pb.d2 : pb.d1;
     float* uout = (j & 1) ? pb.d1 : pb.d2;
-    sweepk_tile<float, ST, K, false>(uin, uout, pb.r32, pb.w32, j * K, pb.nx, pb.ny, pb.pitch32, pb.strips_x,
+    sweepk_tile<float, ST, K, false, ST == 17>(uin, uout, pb.r32, pb.w32, j * K, pb.nx, pb.ny, pb.pitch32, pb.strips_x,
                                      pb.rows_k, it.tile, nullptr);
 }
 
@@ -444,7 +460,7 @@ __global__ __launch_bounds__(256) void batch_correct_kernel(const BatchProblem* 
     const int y1 = min(y0 + pb.rows, pb.ny + 1);
     for (int y = y0; y < y1; ++y) {
         const double un = pb.u[at<double>(pb.pitch, x, y)] + (double)d[at<float>(pb.pitch32, x, y)];
-        store_update<double, ST>(pb.u, pb.pitch, pb.nx, pb.ny, x, y, un);
+        store_update<double, ST, ST == 17>(pb.u, pb.pitch, pb.nx, pb.ny, x, y, un);
     }
 }
 
@@ -489,7 +505,7 @@ __global__ __launch_bounds__(256) void batch_residual_kernel(const BatchProblem*
         acc = fmat<double>(res, res, acc);
         if (active) {
             __builtin_nontemporal_store((float)res, pb.r32 + at<float>(pitch32, x, y));
-            store_update<float, ST>(dz, pitch32, nx, ny, x, y, 0.0f);
+            store_update<float, ST, ST == 17>(dz, pitch32, nx, ny, x, y, 0.0f);
         }
     }
     if (!active) acc = 0.0;
@@ -511,10 +527,10 @@ __global__ __launch_bounds__(256) void segmented_reduce_kernel(const double* __r
 // ------------------------------------------------------------ iterative refinement
 // Residual of the FP64 iterate for the FP32 inner solve: r = g - D^{-1}A u in
 // FP64 (same expression as the sweep), rounded to FP32 into r32; the FP32
-// correction d32 is reset to zero (with its reflected ring for 17 points);
+// correction d32 is reset to zero (with its reflected ring for REFL);
 // per-tile partial sums of r^2 in FP64.
 
-template <int ST>
+template <int ST, bool REFL>
 __global__ __launch_bounds__(256) void ir_residual_kernel(const double* __restrict__ u,
                                                           const double* __restrict__ g, float* __restrict__ r32,
                                                           float* __restrict__ d32, int nx, int ny, int pitch,
@@ -550,7 +566,7 @@ __global__ __launch_bounds__(256) void ir_residual_kernel(const double* __restri
         acc = fmat<double>(res, res, acc);
         if (active) {
             __builtin_nontemporal_store((float)res, r32 + at<float>(pitch32, x, y));
-            store_update<float, ST>(d32, pitch32, nx, ny, x, y, 0.0f);
+            store_update<float, ST, REFL>(d32, pitch32, nx, ny, x, y, 0.0f);
         }
     }
     if (!active) acc = 0.0;
@@ -560,7 +576,8 @@ __global__ __launch_bounds__(256) void ir_residual_kernel(const double* __restri
 
 // u += d over the whole padded frame (rows and columns -1 .. n+2): the
 // Dirichlet ring of d is zero and its outer ring holds the reflection of its
-// interior, so u keeps both properties exactly.
+// interior (homogeneous 17-point data) or zero (boundary data), so u keeps
+// its boundary exactly.
 __global__ __launch_bounds__(256) void ir_correct_kernel(double* __restrict__ u, const float* __restrict__ d,
                                                          int nx, int ny, int pitch, int pitch32, int bx) {
     const int x = (int)(blockIdx.x % bx) * 256 + (int)threadIdx.x - 1;
@@ -582,10 +599,14 @@ __global__ __launch_bounds__(256) void convert_kernel(const Tin* __restrict__ sr
 
 // ------------------------------------------------------------ stage in / out
 
+// Interior of A <- u, of G <- scale * f (zero when f is NULL); of B <- u, or
+// zero when u carries a frame of width fg > 0 (B then holds the zero interior
+// inside the boundary data, whose residual norm is the norm of the lifted
+// right-hand side).  u is nx x ny (fg = 0) or (nx + 2fg) x (ny + 2fg).
 __global__ __launch_bounds__(256) void stage_in_kernel(const double* __restrict__ f, const double* __restrict__ u,
                                                        double scale, double* __restrict__ A, double* __restrict__ B,
                                                        double* __restrict__ G, int nx, int ny, int pitch,
-                                                       int tiles_x, int rows, double* __restrict__ part) {
+                                                       int tiles_x, int rows, double* __restrict__ part, int fg) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int x = tx * (int)blockDim.x + (int)threadIdx.x + 1;
@@ -593,13 +614,15 @@ __global__ __launch_bounds__(256) void stage_in_kernel(const double* __restrict_
     const int y1 = min(y0 + rows, ny + 1);
     double acc = 0.0;
     if (x <= nx) {
+        const size_t ustride = (size_t)nx + 2 * (size_t)fg;
         for (int y = y0; y < y1; ++y) {
             const size_t src = (size_t)(y - 1) * (size_t)nx + (size_t)(x - 1);
+            const size_t usrc = (size_t)(y - 1 + fg) * ustride + (size_t)(x - 1 + fg);
             const size_t dst = at<double>(pitch, x, y);
-            const double uv = u[src];
-            const double gv = scale * f[src];
+            const double uv = u[usrc];
+            const double gv = f ? scale * f[src] : 0.0;
             A[dst] = uv;
-            B[dst] = uv;
+            B[dst] = fg ? 0.0 : uv;
             G[dst] = gv;
             acc = fmat<double>(gv, gv, acc);
         }
@@ -608,10 +631,13 @@ __global__ __launch_bounds__(256) void stage_in_kernel(const double* __restrict_
     if (threadIdx.x == 0) part[tile] = tot;
 }
 
-// Ring values: index k enumerates the 2-wide frame around the interior.
+// Ring values: index k enumerates the 2-wide padded ring around the interior.
+// fg = 0: homogeneous data, the Dirichlet ring zero and the outer ring the odd
+// reflection of u (nx x ny).  fg > 0: u is (nx + 2fg) x (ny + 2fg) and carries
+// the boundary data in a frame of width fg; ring nodes beyond it are zero.
 __global__ __launch_bounds__(256) void ring_kernel(const double* __restrict__ u, double* __restrict__ A,
                                                    double* __restrict__ B, double* __restrict__ G, int nx, int ny,
-                                                   int pitch) {
+                                                   int pitch, int fg) {
     const int W = nx + 4;                 // stored columns -1 .. nx+2
     const int n_rows = 4 * W;             // rows -1, 0, ny+1, ny+2
     const int n_cols = 4 * ny;            // columns -1, 0, nx+1, nx+2 for rows 1..ny
@@ -628,16 +654,21 @@ __global__ __launch_bounds__(256) void ring_kernel(const double* __restrict__ u,
         y = q % ny + 1;
         x = band == 0 ? -1 : band == 1 ? 0 : band == 2 ? nx + 1 : nx + 2;
     }
-    // odd reflection about the Dirichlet nodes 0 and n + 1
-    double sgn = 1.0;
-    int xs = x, ys = y;
-    if (xs < 0) { xs = -xs; sgn = -sgn; }
-    if (xs > nx + 1) { xs = 2 * (nx + 1) - xs; sgn = -sgn; }
-    if (ys < 0) { ys = -ys; sgn = -sgn; }
-    if (ys > ny + 1) { ys = 2 * (ny + 1) - ys; sgn = -sgn; }
     double val = 0.0;
-    if (xs >= 1 && xs <= nx && ys >= 1 && ys <= ny)
-        val = sgn * u[(size_t)(ys - 1) * (size_t)nx + (size_t)(xs - 1)];
+    if (fg > 0) {
+        if (x >= 1 - fg && x <= nx + fg && y >= 1 - fg && y <= ny + fg)
+            val = u[(size_t)(y - 1 + fg) * ((size_t)nx + 2 * (size_t)fg) + (size_t)(x - 1 + fg)];
+    } else {
+        // odd reflection about the Dirichlet nodes 0 and n + 1
+        double sgn = 1.0;
+        int xs = x, ys = y;
+        if (xs < 0) { xs = -xs; sgn = -sgn; }
+        if (xs > nx + 1) { xs = 2 * (nx + 1) - xs; sgn = -sgn; }
+        if (ys < 0) { ys = -ys; sgn = -sgn; }
+        if (ys > ny + 1) { ys = 2 * (ny + 1) - ys; sgn = -sgn; }
+        if (xs >= 1 && xs <= nx && ys >= 1 && ys <= ny)
+            val = sgn * u[(size_t)(ys - 1) * (size_t)nx + (size_t)(xs - 1)];
+    }
     const size_t d = at<double>(pitch, x, y);
     A[d] = val;
     B[d] = val;
@@ -646,12 +677,13 @@ __global__ __launch_bounds__(256) void ring_kernel(const double* __restrict__ u,
 
 // Row-wise kernels use a 1D grid of bx blocks per row: block b covers row
 // b / bx + 1, columns (b % bx) * 256 + 1 ...
+// (u with a frame of width fg: its interior only.)
 __global__ __launch_bounds__(256) void stage_out_kernel(const double* __restrict__ A, double* __restrict__ u,
-                                                        int nx, int ny, int pitch, int bx) {
+                                                        int nx, int ny, int pitch, int bx, int fg) {
     const int x = (int)(blockIdx.x % bx) * 256 + (int)threadIdx.x + 1;
     const int y = (int)(blockIdx.x / bx) + 1;
     if (x > nx || y > ny) return;
-    u[(size_t)(y - 1) * (size_t)nx + (size_t)(x - 1)] = A[at<double>(pitch, x, y)];
+    u[(size_t)(y - 1 + fg) * ((size_t)nx + 2 * (size_t)fg) + (size_t)(x - 1 + fg)] = A[at<double>(pitch, x, y)];
 }
 
 // ------------------------------------------------------------ reduction / apply
@@ -679,23 +711,40 @@ __global__ __launch_bounds__(256) void apply_kernel(const double* __restrict__ A
     au[(size_t)(y - 1) * (size_t)nx + (size_t)(x - 1)] = dscale * (v[R][R] - neighbour_sum<double, ST>(v));
 }
 
+// The 17-point stencil has two kernel families: REFL for homogeneous data
+// (reflected outer ring) and one for boundary data in a frame (L.frame > 0).
+// The 5- and 9-point kernels read only the Dirichlet ring, which is data in
+// both cases.
 template <typename T, int ST, bool WRITE, bool NORM>
 hipError_t launch_tile(const Layout& L, const Tiles& Tl, const T* uin, T* uout, const T* g, const T* w, int widx,
                        double* part, hipStream_t s) {
-    hipLaunchKernelGGL((sweep_kernel<T, ST, WRITE, NORM>), dim3(Tl.count()), dim3(Tl.width), 0, s, uin, uout, g, w,
-                       widx, L.nx, L.ny, L.pitch, Tl.tiles_x, Tl.rows, part);
+    if (ST == 17 && L.frame == 0)
+        hipLaunchKernelGGL((sweep_kernel<T, ST, WRITE, NORM, true>), dim3(Tl.count()), dim3(Tl.width), 0, s, uin,
+                           uout, g, w, widx, L.nx, L.ny, L.pitch, Tl.tiles_x, Tl.rows, part);
+    else
+        hipLaunchKernelGGL((sweep_kernel<T, ST, WRITE, NORM, false>), dim3(Tl.count()), dim3(Tl.width), 0, s, uin,
+                           uout, g, w, widx, L.nx, L.ny, L.pitch, Tl.tiles_x, Tl.rows, part);
     return hipGetLastError();
+}
+
+template <typename T, int ST, int K, bool NORM>
+void launch_k_refl(const Layout& L, const Tiles& Tl, const T* uin, T* uout, const T* g, const T* w, int widx,
+                   double* part, hipStream_t s) {
+    if (ST == 17 && L.frame == 0)
+        hipLaunchKernelGGL((sweepk_kernel<T, ST, K, NORM, true>), dim3(Tl.count()), dim3(256), 0, s, uin, uout, g,
+                           w, widx, L.nx, L.ny, L.pitch, Tl.tiles_x, Tl.rows, part);
+    else
+        hipLaunchKernelGGL((sweepk_kernel<T, ST, K, NORM, false>), dim3(Tl.count()), dim3(256), 0, s, uin, uout, g,
+                           w, widx, L.nx, L.ny, L.pitch, Tl.tiles_x, Tl.rows, part);
 }
 
 template <typename T, int ST, int K>
 hipError_t launch_k(const Layout& L, const Tiles& Tl, const T* uin, T* uout, const T* g, const T* w, int widx,
                     double* part, hipStream_t s) {
     if (part)
-        hipLaunchKernelGGL((sweepk_kernel<T, ST, K, true>), dim3(Tl.count()), dim3(256), 0, s, uin, uout, g, w,
-                           widx, L.nx, L.ny, L.pitch, Tl.tiles_x, Tl.rows, part);
+        launch_k_refl<T, ST, K, true>(L, Tl, uin, uout, g, w, widx, part, s);
     else
-        hipLaunchKernelGGL((sweepk_kernel<T, ST, K, false>), dim3(Tl.count()), dim3(256), 0, s, uin, uout, g, w,
-                           widx, L.nx, L.ny, L.pitch, Tl.tiles_x, Tl.rows, part);
+        launch_k_refl<T, ST, K, false>(L, Tl, uin, uout, g, w, widx, part, s);
     return hipGetLastError();
 }
 
@@ -711,19 +760,21 @@ int frame_blocks(const Layout& L, int* bx) {
 hipError_t launch_stage_in(const Layout& L, const Tiles& T, const double* f, const double* u, double scale,
                            double* A, double* B, double* G, double* part, hipStream_t stream) {
     hipLaunchKernelGGL(stage_in_kernel, dim3(T.count()), dim3(T.width), 0, stream, f, u, scale, A, B, G, L.nx,
-                       L.ny, L.pitch, T.tiles_x, T.rows, part);
+                       L.ny, L.pitch, T.tiles_x, T.rows, part, L.frame);
     return hipGetLastError();
 }
 
 hipError_t launch_ring(const Layout& L, const double* u, double* A, double* B, double* G, hipStream_t stream) {
     const int n = 4 * (L.nx + 4) + 4 * L.ny;
-    hipLaunchKernelGGL(ring_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, u, A, B, G, L.nx, L.ny, L.pitch);
+    hipLaunchKernelGGL(ring_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, u, A, B, G, L.nx, L.ny, L.pitch,
+                       L.frame);
     return hipGetLastError();
 }
 
 hipError_t launch_stage_out(const Layout& L, const double* A, double* u, hipStream_t stream) {
     const int bx = (L.nx + 255) / 256;
-    hipLaunchKernelGGL(stage_out_kernel, dim3(bx * L.ny), dim3(256), 0, stream, A, u, L.nx, L.ny, L.pitch, bx);
+    hipLaunchKernelGGL(stage_out_kernel, dim3(bx * L.ny), dim3(256), 0, stream, A, u, L.nx, L.ny, L.pitch, bx,
+                       L.frame);
     return hipGetLastError();
 }
 
@@ -805,15 +856,19 @@ hipError_t launch_residual(int stencil, const Layout& L, const Tiles& T, const d
 hipError_t launch_ir_residual(int stencil, const Layout& L, const Layout& L32, const Tiles& T, const double* u,
                               const double* g, float* r32, float* d32, double* part, hipStream_t stream) {
     const dim3 grid(T.count()), block(T.width);
-#define CJ_IR_CASE(ST)                                                                                           \
-    case ST:                                                                                                     \
-        hipLaunchKernelGGL(ir_residual_kernel<ST>, grid, block, 0, stream, u, g, r32, d32, L.nx, L.ny, L.pitch, \
-                           L32.pitch, T.tiles_x, T.rows, part);                                                  \
-        break;
+#define CJ_IR_CASE(ST, REFL)                                                                                    \
+        hipLaunchKernelGGL((ir_residual_kernel<ST, REFL>), grid, block, 0, stream, u, g, r32, d32, L.nx, L.ny,  \
+                           L.pitch, L32.pitch, T.tiles_x, T.rows, part);
     switch (stencil) {
-        CJ_IR_CASE(5)
-        CJ_IR_CASE(9)
-        CJ_IR_CASE(17)
+    case 5: CJ_IR_CASE(5, false) break;
+    case 9: CJ_IR_CASE(9, false) break;
+    case 17:
+        if (L.frame == 0) {
+            CJ_IR_CASE(17, true)
+        } else {
+            CJ_IR_CASE(17, false)
+        }
+        break;
     default: return hipErrorInvalidValue;
     }
 #undef CJ_IR_CASE
@@ -915,8 +970,9 @@ hipError_t launch_apply(int stencil, const Layout& L, const double* A, double ds
     return hipGetLastError();
 }
 
-Layout make_layout(int nx, int ny, int elem_bytes) {
+Layout make_layout(int nx, int ny, int elem_bytes, int frame) {
     Layout L;
+    L.frame = frame;
     L.nx = nx;
     L.ny = ny;
     L.elem_bytes = elem_bytes;

@@ -75,10 +75,9 @@ std::vector<int> pair_order(int M) {
     return th;
 }
 
-}  // namespace
-
-bool make_schedule(int stencil, int nx, int ny, double tol, double h, int M_request,
-                   Schedule* s, std::string* err) {
+// Argument checks and the fields every schedule shares.
+bool common_fields(int stencil, int nx, int ny, double tol, double h, int M_request, Schedule* s,
+                   std::string* err) {
     if (stencil != 5 && stencil != 9 && stencil != 17) {
         *err = "stencil must be 5, 9 or 17";
         return false;
@@ -107,6 +106,14 @@ bool make_schedule(int stencil, int nx, int ny, double tol, double h, int M_requ
     s->kmin = kappa_min(stencil, nx, ny);
     s->kmax = kappa_max(stencil);
     s->beta = std::acosh((s->kmax + s->kmin) / (s->kmax - s->kmin));
+    return true;
+}
+
+}  // namespace
+
+bool make_schedule(int stencil, int nx, int ny, double tol, double h, int M_request,
+                   Schedule* s, std::string* err) {
+    if (!common_fields(stencil, nx, ny, tol, h, M_request, s, err)) return false;
     if (M_request > 0) {
         s->M = M_request;
         s->cycles_pred = (int)cycles_for(M_request, s->beta, tol);
@@ -130,6 +137,37 @@ bool make_schedule(int stencil, int nx, int ny, double tol, double h, int M_requ
     s->w.resize(s->M);
     for (int k = 0; k < s->M; ++k)
         s->w[k] = 2.0 / (sum - dif * std::cos((double)th[k] * kPi / (2.0 * s->M)));
+    return true;
+}
+
+// Plain Jacobi (omega = 1, the paper's reference method): the weights are all
+// one and M is only the interval between residual checks.  n_J sweeps meet tol
+// under the bound (1 - kappa_min)^n; by default M is the largest power of two
+// not above n_J / 32, so that the last check overshoots by at most ~3%.
+bool make_jacobi_schedule(int stencil, int nx, int ny, double tol, double h, int M_request, Schedule* s,
+                          std::string* err) {
+    if (!common_fields(stencil, nx, ny, tol, h, M_request, s, err)) return false;
+    const double per_sweep = -std::log1p(-s->kmin);
+    long long nj = 1;
+    if (tol < 1.0) {
+        const double c = std::ceil(std::log(1.0 / tol) / per_sweep);
+        nj = c < 1.0 ? 1 : (c > 4e18 ? (long long)4e18 : (long long)c);
+    }
+    long long M = M_request;
+    if (M == 0) {
+        M = 1;
+        const long long target = nj / 32 > 1 ? nj / 32 : 1;
+        while (2 * M <= target && M < (1LL << 24)) M *= 2;
+    }
+    const long long checks = (nj + M - 1) / M;
+    if (checks > (1LL << 30)) {
+        *err = "Jacobi would need more than 2^30 residual checks at this M and tol";
+        return false;
+    }
+    s->M = (int)M;
+    s->cycles_pred = (int)checks;
+    s->rho = std::exp(-(double)M * per_sweep);
+    s->w.assign((size_t)M, 1.0);
     return true;
 }
 

@@ -205,11 +205,15 @@ cj_status read_sum(cj_plan_s* p, int n, hipStream_t stream, double* out) {
     return CJ_OK;
 }
 
-// Stage-in of f and u; returns sum of G^2.
+// Stage-in of f and u (f may be NULL: G = 0).  Returns the squared norm the
+// relative residual is measured against: sum of G^2 for homogeneous data; with
+// a boundary frame, the squared residual of the zero interior inside the frame
+// (B holds it after stage-in), i.e. of the lifted right-hand side.
 cj_status stage_in(cj_plan_s* p, const double* f, const double* u, hipStream_t stream, double* g2) {
     const double scale = p->s.h * p->s.h / centre_over_s(p->s.stencil);   // D^{-1}
     CJ_HIP(cj::launch_ring(p->L, u, p->A, p->B, p->G, stream));
     CJ_HIP(cj::launch_stage_in(p->L, p->T, f, u, scale, p->A, p->B, p->G, p->part, stream));
+    if (p->L.frame > 0 && f) CJ_HIP(cj::launch_residual(p->s.stencil, p->L, p->T, p->B, p->G, p->part, stream));
     return read_sum(p, p->T.count(), stream, g2);
 }
 
@@ -430,12 +434,17 @@ void cj_options_init(cj_options* opt) {
 cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol, const cj_options* opt, cj_plan_t* out) {
     if (out == nullptr) return fail(CJ_ERR_ARG, "out is NULL");
     *out = nullptr;
-    if (bc != CJ_BC_DIRICHLET0) return fail(CJ_ERR_ARG, "only homogeneous Dirichlet data (bc = 0) is supported");
+    if (bc != CJ_BC_DIRICHLET0 && bc != CJ_BC_DIRICHLET_FRAME)
+        return fail(CJ_ERR_ARG, "bc must be CJ_BC_DIRICHLET0 or CJ_BC_DIRICHLET_FRAME");
     cj_options o;
     cj_options_init(&o);
     if (opt) o = *opt;
     for (int r : o.reserved)
         if (r != 0) return fail(CJ_ERR_ARG, "reserved option fields must be zero");
+    if (o.method != CJ_METHOD_CHEBYSHEV && o.method != CJ_METHOD_JACOBI)
+        return fail(CJ_ERR_ARG, "method must be CJ_METHOD_CHEBYSHEV or CJ_METHOD_JACOBI");
+    const bool jacobi = o.method == CJ_METHOD_JACOBI;
+    if (jacobi && o.precision != CJ_PRECISION_F64) return fail(CJ_ERR_ARG, "CJ_METHOD_JACOBI runs in FP64 only");
     if (o.max_cycles < 0 || o.sweeps_per_launch < 0 || o.tile_rows < 0 || o.inner_M < 0)
         return fail(CJ_ERR_ARG, "negative option");
     if (o.precision != CJ_PRECISION_F64 && o.precision != CJ_PRECISION_F32_REFINE)
@@ -450,7 +459,9 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol, const cj_o
     cj_plan_s* p = new (std::nothrow) cj_plan_s();
     if (!p) return fail(CJ_ERR_NOMEM, "host allocation");
     std::string err;
-    if (!cj::make_schedule(stencil, nx, ny, tol, o.h, o.M, &p->s, &err) ||
+    const bool sched_ok = jacobi ? cj::make_jacobi_schedule(stencil, nx, ny, tol, o.h, o.M, &p->s, &err)
+                                 : cj::make_schedule(stencil, nx, ny, tol, o.h, o.M, &p->s, &err);
+    if (!sched_ok ||
         (mixed && !cj::make_schedule(stencil, nx, ny, tol, o.h, o.inner_M > 0 ? o.inner_M : o.M, &p->sin, &err))) {
         delete p;
         return fail(CJ_ERR_ARG, err);
@@ -470,12 +481,14 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol, const cj_o
     p->opt = o;
     p->precision = o.precision;
     p->max_cycles = o.max_cycles > 0 ? o.max_cycles : (mixed ? 50 : p->s.cycles_pred + 4);
-    p->L = cj::make_layout(nx, ny, 8);
     const int R = radius(stencil);
+    const int frame = bc == CJ_BC_DIRICHLET_FRAME ? R : 0;
+    p->L = cj::make_layout(nx, ny, 8, frame);
     // default depths from measurements at 8192^2 on MI355X (9-point FP64: K = 8 is
     // 3.2x the single-sweep rate; 17-point: K = 3, deeper windows exhaust the registers)
     if (mixed) {
-        p->L32 = cj::make_layout(nx, ny, 4);
+        // the corrections have zero boundary data in the same frame geometry
+        p->L32 = cj::make_layout(nx, ny, 4, frame);
         p->K = 1;
         p->K32 = o.sweeps_per_launch > 0 ? o.sweeps_per_launch : (stencil == 17 ? 4 : 8);
         p->T = cj::make_tiles(nx, ny, p->K32 == 1 ? o.tile_rows : 0);
@@ -546,8 +559,11 @@ cj_status cj_solve(cj_plan_t p, const double* f, double* u, void* stream_, cj_re
     if ((st = stage_in(p, f, u, stream, &g2)) != CJ_OK) return finish(st);
     if (!std::isfinite(g2)) return finish(fail(CJ_ERR_NONFINITE, "f has a NaN or Inf"));
     if (g2 == 0.0) {
-        // f = 0: the solution is u = 0
-        hipError_t e = hipMemsetAsync(u, 0, (size_t)p->s.nx * (size_t)p->s.ny * sizeof(double), stream);
+        // zero (lifted) right-hand side: the solution is the zero interior,
+        // which B holds with a frame
+        hipError_t e = p->L.frame > 0
+                           ? cj::launch_stage_out(p->L, p->B, u, stream)
+                           : hipMemsetAsync(u, 0, (size_t)p->s.nx * (size_t)p->s.ny * sizeof(double), stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return finish(fail(CJ_ERR_HIP, hipGetErrorString(e)));
         return finish(CJ_OK);
@@ -578,12 +594,17 @@ cj_status cj_sweeps(cj_plan_t p, const double* f, double* u, long long n_sweeps,
     double* answer = p->A;
     if (p->mixed()) {
         // the plan's working precision: u and g rounded to FP32, FP32 sweeps
+        // (both iterates carry the boundary: B's ring equals A's)
         CJ_HIP(cj::launch_to_f32(p->L, p->L32, p->A, p->D1, stream));
+        CJ_HIP(cj::launch_to_f32(p->L, p->L32, p->B, p->D2, stream));
         CJ_HIP(cj::launch_to_f32(p->L, p->L32, p->G, p->R32, stream));
         float* cur = p->D1;
         float* nxt = p->D2;
         if ((st = enqueue_f32(p, p->sin.M, 0, n_sweeps, &cur, &nxt, stream)) != CJ_OK) return st;
         CJ_HIP(cj::launch_from_f32(p->L, p->L32, cur, p->A, stream));
+        // the refinement needs the corrections' rings zero again
+        CJ_HIP(hipMemsetAsync(p->D1, 0, p->L32.elems * sizeof(float), stream));
+        CJ_HIP(hipMemsetAsync(p->D2, 0, p->L32.elems * sizeof(float), stream));
     } else {
         double* nxt = p->B;
         if ((st = enqueue_f64(p, 0, n_sweeps, &answer, &nxt, stream)) != CJ_OK) return st;
@@ -616,8 +637,8 @@ cj_status cj_apply(cj_plan_t p, const double* u, double* au, void* stream_) {
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     if ((st = ensure_device(p, stream)) != CJ_OK) return st;
     double g2 = 0.0;
-    // stage u in (f is not needed: stage it from u too, G is unused here)
-    if ((st = stage_in(p, u, u, stream, &g2)) != CJ_OK) return st;
+    // stage u in (f is not needed; G is unused here)
+    if ((st = stage_in(p, nullptr, u, stream, &g2)) != CJ_OK) return st;
     CJ_HIP(cj::launch_apply(p->s.stencil, p->L, p->A, p->D, au, stream));
     CJ_HIP(hipStreamSynchronize(stream));
     return CJ_OK;

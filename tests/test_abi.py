@@ -71,8 +71,9 @@ def test_plan_explicit_M_and_options():
 @pytest.mark.parametrize("args,kw", [
     ((0, 5, 9, 1e-8), {}), ((5, 0, 9, 1e-8), {}), ((5, 5, 7, 1e-8), {}), ((5, 5, 9, 0.0), {}),
     ((5, 5, 9, -1.0), {}), ((5, 5, 9, float("nan")), {}), ((5, 5, 9, 1e-8), {"M": 6}),
-    ((5, 5, 9, 1e-8), {"M": -2}), ((5, 5, 9, 1e-8), {"bc": 1}), ((5, 5, 9, 1e-8), {"max_cycles": -1}),
-    ((5, 5, 9, 1e-8), {"h": -0.5}),
+    ((5, 5, 9, 1e-8), {"M": -2}), ((5, 5, 9, 1e-8), {"bc": 2}), ((5, 5, 9, 1e-8), {"max_cycles": -1}),
+    ((5, 5, 9, 1e-8), {"h": -0.5}), ((5, 5, 9, 1e-8), {"method": 2}),
+    ((5, 5, 9, 1e-8), {"method": 1, "precision": 1}), ((5, 5, 9, 1e-8), {"method": 1, "M": 3}),
 ])
 def test_plan_rejects_bad_arguments(args, kw):
     with pytest.raises(cj.CJError) as e:
@@ -127,3 +128,32 @@ def test_batch_create_host_side():
     assert L.cj_batch_create(0, None, None, None, None, None, ctypes.byref(ctypes.c_void_p())) == cj.CJ_ERR_ARG
     assert L.cj_batch_solve(None, None, None, None, None, None) == cj.CJ_ERR_ARG
     L.cj_batch_destroy(None)
+
+
+@pytest.mark.parametrize("st,n,tol", [(5, 1023, 9.5e-7), (9, 1023, 9.5e-7), (17, 1023, 9.5e-7), (9, 100, 1e-10),
+                                      (17, 31, 1e-3), (5, 1, 0.5)])
+def test_jacobi_plan_matches_oracle(st, n, tol):
+    p = cj.plan(n, n, st, tol, method=cj.JACOBI)
+    o = cjm.plan(n, n, st, tol, method="jacobi")
+    assert (p.M, p.cycles_pred) == (o.M, o.cycles_pred)
+    assert p.weights == [1.0] * p.M
+    p2 = cj.plan(n, n, st, tol, method=cj.JACOBI, M=64)
+    assert (p2.M, p2.cycles_pred) == (64, cjm.plan(n, n, st, tol, M=64, method="jacobi").cycles_pred)
+
+
+def test_frame_plans_on_the_host():
+    for st in (5, 9, 17):
+        p = cj.plan(40, 30, st, 1e-8, bc=cj.BC_FRAME)
+        assert p.frame == (2 if st == 17 else 1)
+        q = cj.plan(40, 30, st, 1e-8)
+        assert (p.M, p.cycles_pred, p.weights) == (q.M, q.cycles_pred, q.weights)
+        cj.plan(40, 30, st, 1e-8, bc=cj.BC_FRAME, precision=cj.F32_REFINE)
+    # batches run Chebyshev-Jacobi only
+    L = cj.lib()
+    o = cj.Options()
+    L.cj_options_init(ctypes.byref(o))
+    o.precision, o.method = cj.F32_REFINE, cj.JACOBI
+    h = ctypes.c_void_p()
+    code = L.cj_batch_create(1, (ctypes.c_int * 1)(10), (ctypes.c_int * 1)(10), (ctypes.c_int * 1)(9),
+                             (ctypes.c_double * 1)(1e-8), ctypes.byref(o), ctypes.byref(h))
+    assert code == cj.CJ_ERR_ARG and not h.value

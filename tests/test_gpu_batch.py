@@ -23,7 +23,7 @@ def _dev(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
 
 
-def _run_batch(torch, shapes, stencils, tols, seed=0, zero=()):
+def _run_batch(torch, shapes, stencils, tols, seed=0, zero=(), infos=None):
     fs, us, hf = [], [], []
     for i, (nx, ny) in enumerate(shapes):
         f = np.zeros((ny, nx)) if i in zero else inputs.gaussian_bumps_rhs(nx, ny, seed=seed + i)
@@ -31,6 +31,8 @@ def _run_batch(torch, shapes, stencils, tols, seed=0, zero=()):
         fs.append(_dev(torch, f))
         us.append(torch.zeros(ny, nx, dtype=torch.float64, device="cuda"))
     b = cj.Batch(shapes, stencils, tols)
+    if infos is not None:
+        infos.extend(b.info(i) for i in range(len(shapes)))
     res, stats = b.solve(fs, us)
     b.destroy()
     return hf, fs, us, res, stats
@@ -42,7 +44,8 @@ def test_batch_matches_single_problem_solves(torch_cuda):
               (40, 40), (257, 65), (64, 300)]
     stencils = [9, 5, 17, 9, 9, 17, 9, 5, 17, 9, 9, 5]
     tols = [1e-8, 1e-10, 1e-8, 1e-10, 1e-8, 1e-8, 1e-9, 1e-6, 1e-10, 1e-8, 1e-8, 1e-10]
-    hf, fs, us, res, stats = _run_batch(torch, shapes, stencils, tols, seed=100, zero=(9,))
+    infos = []
+    hf, fs, us, res, stats = _run_batch(torch, shapes, stencils, tols, seed=100, zero=(9,), infos=infos)
     print("batch stats", stats, flush=True)
     assert stats["supersteps"] > 0
     for i, ((nx, ny), st, tol) in enumerate(zip(shapes, stencils, tols)):
@@ -51,7 +54,10 @@ def test_batch_matches_single_problem_solves(torch_cuda):
         if i == 9:
             assert r["status"] == "ok" and not got.any()
             continue
-        p = cj.plan(nx, ny, st, tol, precision=cj.F32_REFINE)
+        # the batch runs inner cycles of at least 16 sweeps: the single-problem
+        # solve it is compared with uses the same inner cycle and depth
+        p = cj.plan(nx, ny, st, tol, precision=cj.F32_REFINE, inner_M=infos[i]["M"],
+                    sweeps_per_launch=infos[i]["sweeps_per_launch"])
         u1 = torch.zeros(ny, nx, dtype=torch.float64, device="cuda")
         r1 = cj.solve(p, fs[i], u1)
         one = u1.cpu().numpy()
