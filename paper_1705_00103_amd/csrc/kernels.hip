@@ -201,8 +201,9 @@ __global__ __launch_bounds__(256) void sweep_kernel(const T* __restrict__ uin, T
 // performs K updates per point.
 // Outputs shrink by R columns per level on each side of the strip
 // (256 - 2KR output columns) and the tiles overlap in y by KR rows.
-// The row loop is unrolled by the window height W = 2R+1 so that the window
-// rotation is a compile-time renaming of registers.  Workgroups whose halo
+// The row loop is unrolled by a multiple of the window height W = 2R+1 (and
+// of the prefetch depth) so that the window rotation is a compile-time
+// renaming of registers.  Workgroups whose halo
 // reaches the domain boundary take a variant that closes the levels >= 1:
 // with REFL (17-point, homogeneous data) by the Dirichlet zeros and the odd
 // reflections of the level below; otherwise every node outside the interior
@@ -216,10 +217,17 @@ struct March {
     static constexpr int R = Stencil<ST>::R;
     static constexpr int W = 2 * R + 1;
     static constexpr int WOUT = 256 - 2 * K * R;
-    // level-0 rows are fetched PD row steps ahead: W steps for the 3-row
-    // window (a step is shorter than the HBM latency under load), one step for
-    // the 5-row window (its registers are spent on the wider window)
-    static constexpr int PD = (R == 1) ? W : 1;
+    // level-0 rows are fetched PD row steps ahead (a row step is shorter than
+    // the HBM latency under load).  Measured at 8192^2: 3-row windows gain
+    // from 3 steps in FP32 and 2 in FP64, except the 9-point FP64 kernel at
+    // K = 8, which a second row pushes past 256 VGPRs (one wave per SIMD,
+    // 28% slower); 5-row windows take one step (their registers go to the
+    // wider window).
+    static constexpr int PD = (R == 2) ? 1 : sizeof(T) == 4 ? 3 : (ST == 9 && K >= 8) ? 1 : 2;
+    // the row loop is unrolled by U steps, a multiple of both W (window slot
+    // J % W) and PD (prefetch slot J % PD), so that both rotations are static
+    static constexpr int U = (W % PD == 0) ? W : W * PD;
+    static_assert(PD >= 1 && PD <= 3, "prefetch depth");
     T win[K][W][W];   // [level][physical row slot][column x-R .. x+R]
     T gw[K][W];       // g of the lane's column on each window row
     T own[K];         // the lane's value of the row a level produced in this step
@@ -231,8 +239,10 @@ struct March {
     int xsgn[W];      // 1, 0 (Dirichlet column) or -1 (reflection), REFL edge workgroups only
 };
 
-// One row step with compile-time phase J = t mod W.  Level 0 enters slot J at
-// the start of the step; level s >= 1 enters slot J at its end.
+// One row step with compile-time phase J = t mod U.  Level 0 enters window
+// slot J % W at the start of the step; level s >= 1 enters that slot at its
+// end.  The level-0 row of this step was prefetched PD steps earlier into
+// prefetch slot J % PD, which this step refills with the row PD steps ahead.
 template <typename T, int ST, int K, bool NORM, bool REFL, bool EDGE, int J>
 __device__ __forceinline__ void march_step(March<T, ST, K>& S, T (*xch)[March<T, ST, K>::W][256],
                                            const T* __restrict__ uin, T* __restrict__ uout, const T* __restrict__ g,
@@ -242,11 +252,12 @@ __device__ __forceinline__ void march_step(March<T, ST, K>& S, T (*xch)[March<T,
     constexpr int W = 2 * R + 1;
     constexpr int PD = March<T, ST, K>::PD;
     constexpr int P = J % PD;     // prefetch slot of this phase
+    constexpr int JW = J % W;     // window slot of this phase
     const int tid = threadIdx.x;
     const int yl = ybase + t;
 #pragma unroll
-    for (int c = 0; c < W; ++c) S.win[0][J][c] = S.pre[P][c];
-    S.gw[0][J] = S.pg[P];
+    for (int c = 0; c < W; ++c) S.win[0][JW][c] = S.pre[P][c];
+    S.gw[0][JW] = S.pg[P];
     {   // prefetch the level-0 row PD steps ahead, and its g
         const int yr = min(max(yl + PD, -1), ny + 2);
         const T* rowp = uin + (size_t)(yr + 1) * (size_t)pitch;
@@ -258,12 +269,12 @@ __device__ __forceinline__ void march_step(March<T, ST, K>& S, T (*xch)[March<T,
     for (int s = 1; s <= K; ++s) {
         const int Y = yl - (s - 1) - s * R;   // row produced by level s in this step
         // logical window row r (0 = oldest) of level s-1 sits in physical slot
-        // (J + 1 + r) % W for level 0 (filled this step) and (J + r) % W above
+        // (JW + 1 + r) % W for level 0 (filled this step) and (JW + r) % W above
         T v[W][W];
         T gv;
 #pragma unroll
         for (int r = 0; r < W; ++r) {
-            const int ph = (s == 1) ? (J + 1 + r) % W : (J + r) % W;
+            const int ph = (s == 1) ? (JW + 1 + r) % W : (JW + r) % W;
 #pragma unroll
             for (int c = 0; c < W; ++c) v[r][c] = S.win[s - 1][ph][c];
             if (r == R) gv = S.gw[s - 1][ph];
@@ -292,7 +303,7 @@ __device__ __forceinline__ void march_step(March<T, ST, K>& S, T (*xch)[March<T,
         if (!REFL && EDGE && (x < 1 || x > nx || Y < 1 || Y > ny)) un = uc;
         if (NORM && s == 1 && out_col && Y >= Y0 && Y < Y1) acc = fmat<double>((double)res, (double)res, acc);
         if (s < K) {
-            xch[s - 1][J][tid] = un;
+            xch[s - 1][JW][tid] = un;
             S.own[s] = un;
             S.gused[s] = gv;
         } else if (out_col && Y >= Y0 && Y < Y1) {
@@ -309,17 +320,31 @@ __device__ __forceinline__ void march_step(March<T, ST, K>& S, T (*xch)[March<T,
                 if (c == R) {
                     val = S.own[s];
                 } else {
-                    const T e = xch[s - 1][J][S.xsrc[c]];
+                    const T e = xch[s - 1][JW][S.xsrc[c]];
                     if (REFL && EDGE)
                         val = S.xsgn[c] == 0 ? T(0) : (S.xsgn[c] < 0 ? -e : e);
                     else
                         val = e;
                 }
-                S.win[s][J][c] = val;
+                S.win[s][JW][c] = val;
             }
-            S.gw[s][J] = S.gused[s];
+            S.gw[s][JW] = S.gused[s];
         }
     }
+}
+
+// Row steps t + J, t + J + 1, ..., t + U - 1 (compile-time phases).
+template <typename T, int ST, int K, bool NORM, bool REFL, bool EDGE, int J>
+__device__ __forceinline__ void march_steps(March<T, ST, K>& S, T (*xch)[March<T, ST, K>::W][256],
+                                            const T* __restrict__ uin, T* __restrict__ uout,
+                                            const T* __restrict__ g, const T (&om)[K], int t, int ybase, int x,
+                                            int xg, bool out_col, int Y0, int Y1, int nx, int ny, int pitch,
+                                            double& acc) {
+    march_step<T, ST, K, NORM, REFL, EDGE, J>(S, xch, uin, uout, g, om, t + J, ybase, x, xg, out_col, Y0, Y1, nx, ny,
+                                              pitch, acc);
+    if constexpr (J + 1 < March<T, ST, K>::U)
+        march_steps<T, ST, K, NORM, REFL, EDGE, J + 1>(S, xch, uin, uout, g, om, t, ybase, x, xg, out_col, Y0, Y1,
+                                                       nx, ny, pitch, acc);
 }
 
 template <typename T, int ST, int K, bool NORM, bool REFL, bool EDGE>
@@ -327,21 +352,10 @@ __device__ __forceinline__ void march(March<T, ST, K>& S, T (*xch)[March<T, ST, 
                                       const T* __restrict__ uin, T* __restrict__ uout, const T* __restrict__ g,
                                       const T (&om)[K], int ybase, int steps, int x, int xg, bool out_col, int Y0,
                                       int Y1, int nx, int ny, int pitch, double& acc) {
-    constexpr int W = March<T, ST, K>::W;
-    for (int t = 0; t < steps; t += W) {
-        march_step<T, ST, K, NORM, REFL, EDGE, 0>(S, xch, uin, uout, g, om, t, ybase, x, xg, out_col, Y0, Y1, nx, ny,
-                                            pitch, acc);
-        march_step<T, ST, K, NORM, REFL, EDGE, 1>(S, xch, uin, uout, g, om, t + 1, ybase, x, xg, out_col, Y0, Y1, nx,
-                                            ny, pitch, acc);
-        march_step<T, ST, K, NORM, REFL, EDGE, 2>(S, xch, uin, uout, g, om, t + 2, ybase, x, xg, out_col, Y0, Y1, nx,
-                                            ny, pitch, acc);
-        if constexpr (W == 5) {
-            march_step<T, ST, K, NORM, REFL, EDGE, 3>(S, xch, uin, uout, g, om, t + 3, ybase, x, xg, out_col, Y0, Y1,
-                                                nx, ny, pitch, acc);
-            march_step<T, ST, K, NORM, REFL, EDGE, 4>(S, xch, uin, uout, g, om, t + 4, ybase, x, xg, out_col, Y0, Y1,
-                                                nx, ny, pitch, acc);
-        }
-    }
+    constexpr int U = March<T, ST, K>::U;
+    for (int t = 0; t < steps; t += U)
+        march_steps<T, ST, K, NORM, REFL, EDGE, 0>(S, xch, uin, uout, g, om, t, ybase, x, xg, out_col, Y0, Y1, nx,
+                                                   ny, pitch, acc);
 }
 
 // The blocked sweeps of one tile (strip sx, row tile sy = tile / strips_x).
