@@ -46,42 +46,80 @@ __device__ __forceinline__ size_t at(int pitch, int x, int y) {
 //     17-point: 64/300 axis ring 1, -4/300 axis ring 2,
 //               16/300 diagonal ring 1, -1/300 diagonal ring 2.
 // v[dy + R][dx + R] holds u(x + dx, y + dy); nsum returns t.
+//
+// nsum evaluates N independent windows at once, one elementary operation for
+// all N before the next: the temporally blocked kernel hands it the windows of
+// several levels, whose dependency chains then interleave (a lone chain would
+// expose the FP64 pipeline latency at every step).  The operations applied to
+// each window are the same for every N, so results do not depend on N.
 
 template <int ST> struct Stencil;
 
+#define CJ_EACH(stmt) _Pragma("unroll") for (int n = 0; n < N; ++n) { stmt; }
+
 template <> struct Stencil<5> {
     static constexpr int R = 1;
-    template <typename T> __device__ static __forceinline__ T nsum(const T (&v)[3][3]) {
-        const T axis = (v[1][0] + v[1][2]) + (v[0][1] + v[2][1]);
-        return T(0.25) * axis;
+    template <typename T, int N>
+    __device__ static __forceinline__ void nsum(const T (&v)[N][3][3], T (&t)[N]) {
+        T a[N], b[N];
+        CJ_EACH(a[n] = v[n][1][0] + v[n][1][2])
+        CJ_EACH(b[n] = v[n][0][1] + v[n][2][1])
+        CJ_EACH(a[n] = a[n] + b[n])                   // axis
+        CJ_EACH(t[n] = T(0.25) * a[n])
     }
 };
 
 template <> struct Stencil<9> {
     static constexpr int R = 1;
-    template <typename T> __device__ static __forceinline__ T nsum(const T (&v)[3][3]) {
-        const T axis = (v[1][0] + v[1][2]) + (v[0][1] + v[2][1]);
-        const T diag = (v[0][0] + v[2][2]) + (v[2][0] + v[0][2]);
-        return fmat<T>(T(0.2), axis, T(0.05) * diag);
+    template <typename T, int N>
+    __device__ static __forceinline__ void nsum(const T (&v)[N][3][3], T (&t)[N]) {
+        T a[N], b[N], c[N], d[N];
+        CJ_EACH(a[n] = v[n][1][0] + v[n][1][2])
+        CJ_EACH(b[n] = v[n][0][1] + v[n][2][1])
+        CJ_EACH(c[n] = v[n][0][0] + v[n][2][2])
+        CJ_EACH(d[n] = v[n][2][0] + v[n][0][2])
+        CJ_EACH(a[n] = a[n] + b[n])                   // axis
+        CJ_EACH(c[n] = c[n] + d[n])                   // diagonal
+        CJ_EACH(c[n] = T(0.05) * c[n])
+        CJ_EACH(t[n] = fmat<T>(T(0.2), a[n], c[n]))
     }
 };
 
 template <> struct Stencil<17> {
     static constexpr int R = 2;
-    template <typename T> __device__ static __forceinline__ T nsum(const T (&v)[5][5]) {
-        const T axis1 = (v[2][1] + v[2][3]) + (v[1][2] + v[3][2]);
-        const T axis2 = (v[2][0] + v[2][4]) + (v[0][2] + v[4][2]);
-        const T diag1 = (v[1][1] + v[3][3]) + (v[3][1] + v[1][3]);
-        const T diag2 = (v[0][0] + v[4][4]) + (v[4][0] + v[0][4]);
+    template <typename T, int N>
+    __device__ static __forceinline__ void nsum(const T (&v)[N][5][5], T (&t)[N]) {
         const T a1 = T(64.0 / 300.0), a2 = T(-4.0 / 300.0);
         const T d1 = T(16.0 / 300.0), d2 = T(-1.0 / 300.0);
-        return fmat<T>(a1, axis1, fmat<T>(a2, axis2, fmat<T>(d1, diag1, d2 * diag2)));
+        T p[N], q[N], ax1[N], ax2[N], dg1[N], dg2[N];
+        CJ_EACH(p[n] = v[n][2][1] + v[n][2][3])
+        CJ_EACH(q[n] = v[n][1][2] + v[n][3][2])
+        CJ_EACH(ax1[n] = p[n] + q[n])                 // axis, ring 1
+        CJ_EACH(p[n] = v[n][2][0] + v[n][2][4])
+        CJ_EACH(q[n] = v[n][0][2] + v[n][4][2])
+        CJ_EACH(ax2[n] = p[n] + q[n])                 // axis, ring 2
+        CJ_EACH(p[n] = v[n][1][1] + v[n][3][3])
+        CJ_EACH(q[n] = v[n][3][1] + v[n][1][3])
+        CJ_EACH(dg1[n] = p[n] + q[n])                 // diagonal, ring 1
+        CJ_EACH(p[n] = v[n][0][0] + v[n][4][4])
+        CJ_EACH(q[n] = v[n][4][0] + v[n][0][4])
+        CJ_EACH(dg2[n] = p[n] + q[n])                 // diagonal, ring 2
+        CJ_EACH(dg2[n] = d2 * dg2[n])
+        CJ_EACH(dg2[n] = fmat<T>(d1, dg1[n], dg2[n]))
+        CJ_EACH(dg2[n] = fmat<T>(a2, ax2[n], dg2[n]))
+        CJ_EACH(t[n] = fmat<T>(a1, ax1[n], dg2[n]))
     }
 };
 
+#undef CJ_EACH
+
 template <typename T, int ST>
 __device__ __forceinline__ T neighbour_sum(const T (&v)[2 * Stencil<ST>::R + 1][2 * Stencil<ST>::R + 1]) {
-    return Stencil<ST>::template nsum<T>(v);
+    constexpr int W = 2 * Stencil<ST>::R + 1;
+    const T (&v1)[1][W][W] = *reinterpret_cast<const T (*)[1][W][W]>(&v);
+    T t[1];
+    Stencil<ST>::template nsum<T, 1>(v1, t);
+    return t[0];
 }
 
 // Hardware dispatches workgroup b to XCD b % 8.  Give every XCD a contiguous
@@ -228,6 +266,12 @@ struct March {
     // J % W) and PD (prefetch slot J % PD), so that both rotations are static
     static constexpr int U = (W % PD == 0) ? W : W * PD;
     static_assert(PD >= 1 && PD <= 3, "prefetch depth");
+    // levels whose updates are evaluated side by side.  Measured at 8192^2:
+    // one level at a time is fastest (9-point FP64 K = 8: 73.4 us per sweep,
+    // 76-78 us for groups of 2, 3, 4 or 8) -- the split pair sums of nsum
+    // already give each window four independent chains, and wider groups
+    // cost registers
+    static constexpr int ILP = 1;
     T win[K][W][W];   // [level][physical row slot][column x-R .. x+R]
     T gw[K][W];       // g of the lane's column on each window row
     T own[K];         // the lane's value of the row a level produced in this step
@@ -238,6 +282,80 @@ struct March {
     int xsrc[W];      // exchange source lanes for the x +- R neighbours
     int xsgn[W];      // 1, 0 (Dirichlet column) or -1 (reflection), REFL edge workgroups only
 };
+
+// Levels S0 .. S0 + N - 1 of one row step (window slot JW), N = min(ILP,
+// K - S0 + 1): their windows are independent, so their updates are evaluated
+// side by side (see nsum), then each is exchanged or stored.
+template <typename T, int ST, int K, bool NORM, bool REFL, bool EDGE, int JW, int S0>
+__device__ __forceinline__ void march_levels(March<T, ST, K>& S, T (*xch)[March<T, ST, K>::W][256],
+                                             T* __restrict__ uout, const T (&om)[K], int yl, int x, bool out_col,
+                                             int Y0, int Y1, int nx, int ny, int pitch, double& acc) {
+    constexpr int R = Stencil<ST>::R;
+    constexpr int W = 2 * R + 1;
+    constexpr int N = (K - S0 + 1) < March<T, ST, K>::ILP ? (K - S0 + 1) : March<T, ST, K>::ILP;
+    const int tid = threadIdx.x;
+    T v[N][W][W];
+    T gv[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        const int s = S0 + n;
+        const int Y = yl - (s - 1) - s * R;   // row produced by level s in this step
+        // logical window row r (0 = oldest) of level s-1 sits in physical slot
+        // (JW + 1 + r) % W for level 0 (filled this step) and (JW + r) % W above
+#pragma unroll
+        for (int r = 0; r < W; ++r) {
+            const int ph = (s == 1) ? (JW + 1 + r) % W : (JW + r) % W;
+#pragma unroll
+            for (int c = 0; c < W; ++c) v[n][r][c] = S.win[s - 1][ph][c];
+            if (r == R) gv[n] = S.gw[s - 1][ph];
+        }
+        if (REFL && EDGE && s > 1 && (Y - R < 1 || Y + R > ny)) {
+            // rows beyond the interior: Dirichlet zeros, second ring by odd reflection
+#pragma unroll
+            for (int r = 0; r < W; ++r) {
+                const int q = Y - R + r;
+                if (q == 0 || q == ny + 1) {
+#pragma unroll
+                    for (int c = 0; c < W; ++c) v[n][r][c] = T(0);
+                } else if (R == 2 && q == -1 && r + 2 < W) {
+#pragma unroll
+                    for (int c = 0; c < W; ++c) v[n][r][c] = -v[n][r + 2][c];
+                } else if (R == 2 && q == ny + 2 && r >= 2) {
+#pragma unroll
+                    for (int c = 0; c < W; ++c) v[n][r][c] = -v[n][r - 2][c];
+                }
+            }
+        }
+    }
+    T t[N], res[N], un[N];
+    Stencil<ST>::template nsum<T, N>(v, t);
+#pragma unroll
+    for (int n = 0; n < N; ++n) res[n] = gv[n] + t[n];
+#pragma unroll
+    for (int n = 0; n < N; ++n) res[n] = res[n] - v[n][R][R];
+#pragma unroll
+    for (int n = 0; n < N; ++n) un[n] = fmat<T>(om[S0 + n - 1], res[n], v[n][R][R]);
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        const int s = S0 + n;
+        const int Y = yl - (s - 1) - s * R;
+        const T uc = v[n][R][R];
+        T u1 = un[n];
+        // boundary data: a node outside the interior keeps its value
+        if (!REFL && EDGE && (x < 1 || x > nx || Y < 1 || Y > ny)) u1 = uc;
+        if (NORM && s == 1 && out_col && Y >= Y0 && Y < Y1) acc = fmat<double>((double)res[n], (double)res[n], acc);
+        if (s < K) {
+            xch[s - 1][JW][tid] = u1;
+            S.own[s] = u1;
+            S.gused[s] = gv[n];
+        } else if (out_col && Y >= Y0 && Y < Y1) {
+            store_update<T, ST, REFL>(uout, pitch, nx, ny, x, Y, u1);
+        }
+    }
+    if constexpr (S0 + N <= K)
+        march_levels<T, ST, K, NORM, REFL, EDGE, JW, S0 + N>(S, xch, uout, om, yl, x, out_col, Y0, Y1, nx, ny, pitch,
+                                                             acc);
+}
 
 // One row step with compile-time phase J = t mod U.  Level 0 enters window
 // slot J % W at the start of the step; level s >= 1 enters that slot at its
@@ -265,51 +383,7 @@ __device__ __forceinline__ void march_step(March<T, ST, K>& S, T (*xch)[March<T,
         for (int c = 0; c < W; ++c) S.pre[P][c] = rowp[S.lcol[c]];
         S.pg[P] = __builtin_nontemporal_load(g + at<T>(pitch, xg, yr));
     }
-#pragma unroll
-    for (int s = 1; s <= K; ++s) {
-        const int Y = yl - (s - 1) - s * R;   // row produced by level s in this step
-        // logical window row r (0 = oldest) of level s-1 sits in physical slot
-        // (JW + 1 + r) % W for level 0 (filled this step) and (JW + r) % W above
-        T v[W][W];
-        T gv;
-#pragma unroll
-        for (int r = 0; r < W; ++r) {
-            const int ph = (s == 1) ? (JW + 1 + r) % W : (JW + r) % W;
-#pragma unroll
-            for (int c = 0; c < W; ++c) v[r][c] = S.win[s - 1][ph][c];
-            if (r == R) gv = S.gw[s - 1][ph];
-        }
-        if (REFL && EDGE && s > 1 && (Y - R < 1 || Y + R > ny)) {
-            // rows beyond the interior: Dirichlet zeros, second ring by odd reflection
-#pragma unroll
-            for (int r = 0; r < W; ++r) {
-                const int q = Y - R + r;
-                if (q == 0 || q == ny + 1) {
-#pragma unroll
-                    for (int c = 0; c < W; ++c) v[r][c] = T(0);
-                } else if (R == 2 && q == -1 && r + 2 < W) {
-#pragma unroll
-                    for (int c = 0; c < W; ++c) v[r][c] = -v[r + 2][c];
-                } else if (R == 2 && q == ny + 2 && r >= 2) {
-#pragma unroll
-                    for (int c = 0; c < W; ++c) v[r][c] = -v[r - 2][c];
-                }
-            }
-        }
-        const T uc = v[R][R];
-        const T res = (gv + neighbour_sum<T, ST>(v)) - uc;
-        T un = fmat<T>(om[s - 1], res, uc);
-        // boundary data: a node outside the interior keeps its value
-        if (!REFL && EDGE && (x < 1 || x > nx || Y < 1 || Y > ny)) un = uc;
-        if (NORM && s == 1 && out_col && Y >= Y0 && Y < Y1) acc = fmat<double>((double)res, (double)res, acc);
-        if (s < K) {
-            xch[s - 1][JW][tid] = un;
-            S.own[s] = un;
-            S.gused[s] = gv;
-        } else if (out_col && Y >= Y0 && Y < Y1) {
-            store_update<T, ST, REFL>(uout, pitch, nx, ny, x, Y, un);
-        }
-    }
+    march_levels<T, ST, K, NORM, REFL, EDGE, JW, 1>(S, xch, uout, om, yl, x, out_col, Y0, Y1, nx, ny, pitch, acc);
     if (K > 1) {
         __syncthreads();
 #pragma unroll
