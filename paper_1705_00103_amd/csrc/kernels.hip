@@ -45,81 +45,67 @@ __device__ __forceinline__ size_t at(int pitch, int x, int y) {
 //     9-point : 4/20 axis, 1/20 diagonal
 //     17-point: 64/300 axis ring 1, -4/300 axis ring 2,
 //               16/300 diagonal ring 1, -1/300 diagonal ring 2.
-// v[dy + R][dx + R] holds u(x + dx, y + dy); nsum returns t.
-//
-// nsum evaluates N independent windows at once, one elementary operation for
-// all N before the next: the temporally blocked kernel hands it the windows of
-// several levels, whose dependency chains then interleave (a lone chain would
-// expose the FP64 pipeline latency at every step).  The operations applied to
-// each window are the same for every N, so results do not depend on N.
+// Every coefficient multiplies a centre value or a symmetric pair of one
+// window row, so a row y + dy enters as its summary
+//     C = u(x, y + dy),  P_k = u(x - k, y + dy) + u(x + k, y + dy),  k = 1..R,
+// and t combines the summaries s[dy + R] = {C, P_1, .., P_R}:
+//     5-point : 1/4 (P_1[0] + (C[-1] + C[+1]))
+//     9-point : 1/5 (P_1[0] + (C[-1] + C[+1])) + 1/20 (P_1[-1] + P_1[+1])
+//     17-point: (64/300 (P_1[0] + (C[-1] + C[+1])) - 4/300 (P_2[0] + (C[-2] + C[+2])))
+//               + (16/300 (P_1[-1] + P_1[+1]) - 1/300 (P_2[-2] + P_2[+2])).
+// The grouping keeps the dependency chains short: the FP64 pipeline latency,
+// not the operation count, bounds the blocked kernel at two waves per SIMD.
+// The temporally blocked kernel keeps only the summaries of its window rows
+// (R + 1 values instead of 2R + 1) and forms each pair sum once per row; every
+// kernel evaluates t through these two functions, so all produce the same bits.
 
 template <int ST> struct Stencil;
 
-#define CJ_EACH(stmt) _Pragma("unroll") for (int n = 0; n < N; ++n) { stmt; }
-
 template <> struct Stencil<5> {
     static constexpr int R = 1;
-    template <typename T, int N>
-    __device__ static __forceinline__ void nsum(const T (&v)[N][3][3], T (&t)[N]) {
-        T a[N], b[N];
-        CJ_EACH(a[n] = v[n][1][0] + v[n][1][2])
-        CJ_EACH(b[n] = v[n][0][1] + v[n][2][1])
-        CJ_EACH(a[n] = a[n] + b[n])                   // axis
-        CJ_EACH(t[n] = T(0.25) * a[n])
+    template <typename T> __device__ static __forceinline__ T combine(const T (&s)[3][2]) {
+        return T(0.25) * (s[1][1] + (s[0][0] + s[2][0]));
     }
 };
 
 template <> struct Stencil<9> {
     static constexpr int R = 1;
-    template <typename T, int N>
-    __device__ static __forceinline__ void nsum(const T (&v)[N][3][3], T (&t)[N]) {
-        T a[N], b[N], c[N], d[N];
-        CJ_EACH(a[n] = v[n][1][0] + v[n][1][2])
-        CJ_EACH(b[n] = v[n][0][1] + v[n][2][1])
-        CJ_EACH(c[n] = v[n][0][0] + v[n][2][2])
-        CJ_EACH(d[n] = v[n][2][0] + v[n][0][2])
-        CJ_EACH(a[n] = a[n] + b[n])                   // axis
-        CJ_EACH(c[n] = c[n] + d[n])                   // diagonal
-        CJ_EACH(c[n] = T(0.05) * c[n])
-        CJ_EACH(t[n] = fmat<T>(T(0.2), a[n], c[n]))
+    template <typename T> __device__ static __forceinline__ T combine(const T (&s)[3][2]) {
+        const T axis = s[1][1] + (s[0][0] + s[2][0]);
+        const T diag = s[0][1] + s[2][1];
+        return fmat<T>(T(0.2), axis, T(0.05) * diag);
     }
 };
 
 template <> struct Stencil<17> {
     static constexpr int R = 2;
-    template <typename T, int N>
-    __device__ static __forceinline__ void nsum(const T (&v)[N][5][5], T (&t)[N]) {
+    template <typename T> __device__ static __forceinline__ T combine(const T (&s)[5][3]) {
+        const T axis1 = s[2][1] + (s[1][0] + s[3][0]);
+        const T axis2 = s[2][2] + (s[0][0] + s[4][0]);
+        const T diag1 = s[1][1] + s[3][1];
+        const T diag2 = s[0][2] + s[4][2];
         const T a1 = T(64.0 / 300.0), a2 = T(-4.0 / 300.0);
         const T d1 = T(16.0 / 300.0), d2 = T(-1.0 / 300.0);
-        T p[N], q[N], ax1[N], ax2[N], dg1[N], dg2[N];
-        CJ_EACH(p[n] = v[n][2][1] + v[n][2][3])
-        CJ_EACH(q[n] = v[n][1][2] + v[n][3][2])
-        CJ_EACH(ax1[n] = p[n] + q[n])                 // axis, ring 1
-        CJ_EACH(p[n] = v[n][2][0] + v[n][2][4])
-        CJ_EACH(q[n] = v[n][0][2] + v[n][4][2])
-        CJ_EACH(ax2[n] = p[n] + q[n])                 // axis, ring 2
-        CJ_EACH(p[n] = v[n][1][1] + v[n][3][3])
-        CJ_EACH(q[n] = v[n][3][1] + v[n][1][3])
-        CJ_EACH(dg1[n] = p[n] + q[n])                 // diagonal, ring 1
-        CJ_EACH(p[n] = v[n][0][0] + v[n][4][4])
-        CJ_EACH(q[n] = v[n][4][0] + v[n][0][4])
-        CJ_EACH(dg2[n] = p[n] + q[n])                 // diagonal, ring 2
-        CJ_EACH(dg2[n] = d2 * dg2[n])
-        CJ_EACH(dg2[n] = fmat<T>(d1, dg1[n], dg2[n]))
-        CJ_EACH(dg2[n] = fmat<T>(a2, ax2[n], dg2[n]))
-        CJ_EACH(t[n] = fmat<T>(a1, ax1[n], dg2[n]))
+        return fmat<T>(a1, axis1, a2 * axis2) + fmat<T>(d1, diag1, d2 * diag2);
     }
 };
 
-#undef CJ_EACH
+// Summary {C, P_1, .., P_R} of one window row (its 2R + 1 values around x).
+template <typename T, int R>
+__device__ __forceinline__ void row_summary(const T (&row)[2 * R + 1], T (&sm)[R + 1]) {
+    sm[0] = row[R];
+#pragma unroll
+    for (int k = 1; k <= R; ++k) sm[k] = row[R - k] + row[R + k];
+}
 
+// t of a full window, v[dy + R][dx + R] = u(x + dx, y + dy).
 template <typename T, int ST>
 __device__ __forceinline__ T neighbour_sum(const T (&v)[2 * Stencil<ST>::R + 1][2 * Stencil<ST>::R + 1]) {
-    constexpr int W = 2 * Stencil<ST>::R + 1;
-    const T (&v1)[1][W][W] = *reinterpret_cast<const T (*)[1][W][W]>(&v);
-    T t[1];
-    Stencil<ST>::template nsum<T, 1>(v1, t);
-    return t[0];
+    constexpr int R = Stencil<ST>::R;
+    T sm[2 * R + 1][R + 1];
+#pragma unroll
+    for (int r = 0; r < 2 * R + 1; ++r) row_summary<T, R>(v[r], sm[r]);
+    return Stencil<ST>::template combine<T>(sm);
 }
 
 // Hardware dispatches workgroup b to XCD b % 8.  Give every XCD a contiguous
@@ -232,9 +218,9 @@ __global__ __launch_bounds__(256) void sweep_kernel(const T* __restrict__ uin, T
 // only needs rows of the level below that were finished in an earlier step:
 // one barrier per row step suffices.  Level 0 comes from HBM (the row and its
 // x +- R neighbours), levels 1..K-1 are exchanged between lanes through LDS,
-// and every lane keeps a (2R+1) x (2R+1) register window per level, each row
-// tagged with the lane's value of g on that row (the g a level used for a row
-// is the g the next level needs on it).  Only level K is written back, so one
+// and every lane keeps a register window of 2R+1 row summaries per level
+// (see Stencil), each row tagged with the lane's value of g on that row (the
+// g a level used for a row is the g the next level needs on it).  Only level K is written back, so one
 // launch moves one read of u and g and one write of u per grid point and
 // performs K updates per point.
 // Outputs shrink by R columns per level on each side of the strip
@@ -257,22 +243,21 @@ struct March {
     static constexpr int WOUT = 256 - 2 * K * R;
     // level-0 rows are fetched PD row steps ahead (a row step is shorter than
     // the HBM latency under load).  Measured at 8192^2: 3-row windows gain
-    // from 3 steps in FP32 and 2 in FP64, except the 9-point FP64 kernel at
-    // K = 8, which a second row pushes past 256 VGPRs (one wave per SIMD,
-    // 28% slower); 5-row windows take one step (their registers go to the
-    // wider window).
-    static constexpr int PD = (R == 2) ? 1 : sizeof(T) == 4 ? 3 : (ST == 9 && K >= 8) ? 1 : 2;
+    // from 3 steps in FP32 and 2 in FP64 (9-point K = 8: 75.3 -> 70.1 us per
+    // sweep); 5-row windows take one step (their registers go to the wider
+    // window).
+    static constexpr int PD = (R == 2) ? 1 : sizeof(T) == 4 ? 3 : 2;
     // the row loop is unrolled by U steps, a multiple of both W (window slot
     // J % W) and PD (prefetch slot J % PD), so that both rotations are static
     static constexpr int U = (W % PD == 0) ? W : W * PD;
     static_assert(PD >= 1 && PD <= 3, "prefetch depth");
-    // levels whose updates are evaluated side by side.  Measured at 8192^2:
-    // one level at a time is fastest (9-point FP64 K = 8: 73.4 us per sweep,
-    // 76-78 us for groups of 2, 3, 4 or 8) -- the split pair sums of nsum
-    // already give each window four independent chains, and wider groups
-    // cost registers
-    static constexpr int ILP = 1;
-    T win[K][W][W];   // [level][physical row slot][column x-R .. x+R]
+    // Window rows are kept as their summaries {C, P_1 .. P_R}: fewer
+    // registers than the 2R + 1 values, and each pair sum is formed once.
+    // Measured at 8192^2, FP64: this lets 9-point K = 10 and 17-point K = 4 run
+    // at two waves per SIMD (9-point 73.4 -> 68.6 us per sweep, 17-point
+    // 182.6 -> 152.5 us).
+    static constexpr int NV = R + 1;
+    T win[K][W][NV];      // [level][physical row slot][row summary]
     T gw[K][W];       // g of the lane's column on each window row
     T own[K];         // the lane's value of the row a level produced in this step
     T gused[K];       // the g it used
@@ -282,80 +267,6 @@ struct March {
     int xsrc[W];      // exchange source lanes for the x +- R neighbours
     int xsgn[W];      // 1, 0 (Dirichlet column) or -1 (reflection), REFL edge workgroups only
 };
-
-// Levels S0 .. S0 + N - 1 of one row step (window slot JW), N = min(ILP,
-// K - S0 + 1): their windows are independent, so their updates are evaluated
-// side by side (see nsum), then each is exchanged or stored.
-template <typename T, int ST, int K, bool NORM, bool REFL, bool EDGE, int JW, int S0>
-__device__ __forceinline__ void march_levels(March<T, ST, K>& S, T (*xch)[March<T, ST, K>::W][256],
-                                             T* __restrict__ uout, const T (&om)[K], int yl, int x, bool out_col,
-                                             int Y0, int Y1, int nx, int ny, int pitch, double& acc) {
-    constexpr int R = Stencil<ST>::R;
-    constexpr int W = 2 * R + 1;
-    constexpr int N = (K - S0 + 1) < March<T, ST, K>::ILP ? (K - S0 + 1) : March<T, ST, K>::ILP;
-    const int tid = threadIdx.x;
-    T v[N][W][W];
-    T gv[N];
-#pragma unroll
-    for (int n = 0; n < N; ++n) {
-        const int s = S0 + n;
-        const int Y = yl - (s - 1) - s * R;   // row produced by level s in this step
-        // logical window row r (0 = oldest) of level s-1 sits in physical slot
-        // (JW + 1 + r) % W for level 0 (filled this step) and (JW + r) % W above
-#pragma unroll
-        for (int r = 0; r < W; ++r) {
-            const int ph = (s == 1) ? (JW + 1 + r) % W : (JW + r) % W;
-#pragma unroll
-            for (int c = 0; c < W; ++c) v[n][r][c] = S.win[s - 1][ph][c];
-            if (r == R) gv[n] = S.gw[s - 1][ph];
-        }
-        if (REFL && EDGE && s > 1 && (Y - R < 1 || Y + R > ny)) {
-            // rows beyond the interior: Dirichlet zeros, second ring by odd reflection
-#pragma unroll
-            for (int r = 0; r < W; ++r) {
-                const int q = Y - R + r;
-                if (q == 0 || q == ny + 1) {
-#pragma unroll
-                    for (int c = 0; c < W; ++c) v[n][r][c] = T(0);
-                } else if (R == 2 && q == -1 && r + 2 < W) {
-#pragma unroll
-                    for (int c = 0; c < W; ++c) v[n][r][c] = -v[n][r + 2][c];
-                } else if (R == 2 && q == ny + 2 && r >= 2) {
-#pragma unroll
-                    for (int c = 0; c < W; ++c) v[n][r][c] = -v[n][r - 2][c];
-                }
-            }
-        }
-    }
-    T t[N], res[N], un[N];
-    Stencil<ST>::template nsum<T, N>(v, t);
-#pragma unroll
-    for (int n = 0; n < N; ++n) res[n] = gv[n] + t[n];
-#pragma unroll
-    for (int n = 0; n < N; ++n) res[n] = res[n] - v[n][R][R];
-#pragma unroll
-    for (int n = 0; n < N; ++n) un[n] = fmat<T>(om[S0 + n - 1], res[n], v[n][R][R]);
-#pragma unroll
-    for (int n = 0; n < N; ++n) {
-        const int s = S0 + n;
-        const int Y = yl - (s - 1) - s * R;
-        const T uc = v[n][R][R];
-        T u1 = un[n];
-        // boundary data: a node outside the interior keeps its value
-        if (!REFL && EDGE && (x < 1 || x > nx || Y < 1 || Y > ny)) u1 = uc;
-        if (NORM && s == 1 && out_col && Y >= Y0 && Y < Y1) acc = fmat<double>((double)res[n], (double)res[n], acc);
-        if (s < K) {
-            xch[s - 1][JW][tid] = u1;
-            S.own[s] = u1;
-            S.gused[s] = gv[n];
-        } else if (out_col && Y >= Y0 && Y < Y1) {
-            store_update<T, ST, REFL>(uout, pitch, nx, ny, x, Y, u1);
-        }
-    }
-    if constexpr (S0 + N <= K)
-        march_levels<T, ST, K, NORM, REFL, EDGE, JW, S0 + N>(S, xch, uout, om, yl, x, out_col, Y0, Y1, nx, ny, pitch,
-                                                             acc);
-}
 
 // One row step with compile-time phase J = t mod U.  Level 0 enters window
 // slot J % W at the start of the step; level s >= 1 enters that slot at its
@@ -373,8 +284,7 @@ __device__ __forceinline__ void march_step(March<T, ST, K>& S, T (*xch)[March<T,
     constexpr int JW = J % W;     // window slot of this phase
     const int tid = threadIdx.x;
     const int yl = ybase + t;
-#pragma unroll
-    for (int c = 0; c < W; ++c) S.win[0][JW][c] = S.pre[P][c];
+    row_summary<T, R>(S.pre[P], S.win[0][JW]);
     S.gw[0][JW] = S.pg[P];
     {   // prefetch the level-0 row PD steps ahead, and its g
         const int yr = min(max(yl + PD, -1), ny + 2);
@@ -383,25 +293,69 @@ __device__ __forceinline__ void march_step(March<T, ST, K>& S, T (*xch)[March<T,
         for (int c = 0; c < W; ++c) S.pre[P][c] = rowp[S.lcol[c]];
         S.pg[P] = __builtin_nontemporal_load(g + at<T>(pitch, xg, yr));
     }
-    march_levels<T, ST, K, NORM, REFL, EDGE, JW, 1>(S, xch, uout, om, yl, x, out_col, Y0, Y1, nx, ny, pitch, acc);
+#pragma unroll
+    for (int s = 1; s <= K; ++s) {
+        const int Y = yl - (s - 1) - s * R;   // row produced by level s in this step
+        // logical window row r (0 = oldest) of level s-1 sits in physical slot
+        // (JW + 1 + r) % W for level 0 (filled this step) and (JW + r) % W above
+        T sm[W][R + 1];
+        T gv;
+#pragma unroll
+        for (int r = 0; r < W; ++r) {
+            const int ph = (s == 1) ? (JW + 1 + r) % W : (JW + r) % W;
+#pragma unroll
+            for (int k = 0; k <= R; ++k) sm[r][k] = S.win[s - 1][ph][k];
+            if (r == R) gv = S.gw[s - 1][ph];
+        }
+        if (REFL && EDGE && s > 1 && (Y - R < 1 || Y + R > ny)) {
+            // rows beyond the interior: Dirichlet zeros, second ring by odd reflection
+#pragma unroll
+            for (int r = 0; r < W; ++r) {
+                const int q = Y - R + r;
+                if (q == 0 || q == ny + 1) {
+#pragma unroll
+                    for (int k = 0; k <= R; ++k) sm[r][k] = T(0);
+                } else if (R == 2 && q == -1 && r + 2 < W) {
+#pragma unroll
+                    for (int k = 0; k <= R; ++k) sm[r][k] = -sm[r + 2][k];
+                } else if (R == 2 && q == ny + 2 && r >= 2) {
+#pragma unroll
+                    for (int k = 0; k <= R; ++k) sm[r][k] = -sm[r - 2][k];
+                }
+            }
+        }
+        const T uc = sm[R][0];
+        const T res = (gv + Stencil<ST>::template combine<T>(sm)) - uc;
+        T un = fmat<T>(om[s - 1], res, uc);
+        // boundary data: a node outside the interior keeps its value
+        if (!REFL && EDGE && (x < 1 || x > nx || Y < 1 || Y > ny)) un = uc;
+        if (NORM && s == 1 && out_col && Y >= Y0 && Y < Y1) acc = fmat<double>((double)res, (double)res, acc);
+        if (s < K) {
+            xch[s - 1][JW][tid] = un;
+            S.own[s] = un;
+            S.gused[s] = gv;
+        } else if (out_col && Y >= Y0 && Y < Y1) {
+            store_update<T, ST, REFL>(uout, pitch, nx, ny, x, Y, un);
+        }
+    }
     if (K > 1) {
         __syncthreads();
 #pragma unroll
         for (int s = 1; s < K; ++s) {
+            T row[W];
 #pragma unroll
             for (int c = 0; c < W; ++c) {
-                T val;
                 if (c == R) {
-                    val = S.own[s];
+                    row[c] = S.own[s];
                 } else {
                     const T e = xch[s - 1][JW][S.xsrc[c]];
                     if (REFL && EDGE)
-                        val = S.xsgn[c] == 0 ? T(0) : (S.xsgn[c] < 0 ? -e : e);
+                        row[c] = S.xsgn[c] == 0 ? T(0) : (S.xsgn[c] < 0 ? -e : e);
                     else
-                        val = e;
+                        row[c] = e;
                 }
-                S.win[s][JW][c] = val;
             }
+            row_summary<T, R>(row, S.win[s][JW]);
             S.gw[s][JW] = S.gused[s];
         }
     }
@@ -477,7 +431,7 @@ __device__ __forceinline__ void sweepk_tile(const T* __restrict__ uin, T* __rest
         for (int r = 0; r < W; ++r) {
             S.gw[s][r] = T(0);
 #pragma unroll
-            for (int c = 0; c < W; ++c) S.win[s][r][c] = T(0);
+            for (int k = 0; k < MS::NV; ++k) S.win[s][r][k] = T(0);
         }
     }
     const int ybase = Y0 - K * R;   // level-0 row entering at step 0
@@ -904,7 +858,7 @@ bool sweepk_supported(int stencil, int K, int elem_bytes) {
         return K == 2 || K == 4 || K == 8;
     }
     if (stencil == 17) return K == 2 || K == 3 || K == 4;
-    return K == 2 || K == 3 || K == 4 || K == 6 || K == 8;
+    return K == 2 || K == 3 || K == 4 || K == 6 || K == 8 || K == 10;
 }
 
 hipError_t launch_sweepk(int stencil, int K, const Layout& L, const Tiles& Tl, const double* uin,
@@ -913,8 +867,8 @@ hipError_t launch_sweepk(int stencil, int K, const Layout& L, const Tiles& Tl, c
 #define CJ_K_CASE(ST, KK) \
     if (stencil == ST && K == KK) return launch_k<double, ST, KK>(L, Tl, uin, uout, g, w, widx, part, stream);
     CJ_K_CASE(5, 2) CJ_K_CASE(5, 3) CJ_K_CASE(5, 4) CJ_K_CASE(5, 6) CJ_K_CASE(5, 8)
-    CJ_K_CASE(9, 2) CJ_K_CASE(9, 3) CJ_K_CASE(9, 4) CJ_K_CASE(9, 6) CJ_K_CASE(9, 8)
-    CJ_K_CASE(17, 2) CJ_K_CASE(17, 3) CJ_K_CASE(17, 4)
+    CJ_K_CASE(9, 2) CJ_K_CASE(9, 3) CJ_K_CASE(9, 4) CJ_K_CASE(9, 6) CJ_K_CASE(9, 8) CJ_K_CASE(9, 10)
+    CJ_K_CASE(5, 10) CJ_K_CASE(17, 2) CJ_K_CASE(17, 3) CJ_K_CASE(17, 4)
 #undef CJ_K_CASE
     return hipErrorInvalidValue;
 }

@@ -219,8 +219,9 @@ cj_status stage_in(cj_plan_s* p, const double* f, const double* u, hipStream_t s
 
 // Enqueues sweeps [first, first + n) of a cyclic schedule of length M with
 // device weights w, on layout L with right-hand side g, starting from *cur,
-// in launches of K sweeps (single sweeps where a launch would run past the end
-// of the cycle or of the range).  If norm_parts != nullptr (FP64 only) the
+// in launches of K sweeps; where a launch would run past the end of the cycle
+// or of the range, the k < K sweeps left run as one blocked launch of depth k
+// if there is one, else as single sweeps.  If norm_parts != nullptr (FP64 only) the
 // first launch also produces the residual partials of its input and
 // *norm_parts receives their count.  *launches counts the launches.
 template <typename T>
@@ -237,6 +238,9 @@ cj_status enqueue_sweeps(cj_plan_s* p, int M, int K, const cj::Layout& L, const 
         if (k == K && K > 1) {
             CJ_HIP(cj::launch_sweepk(p->s.stencil, K, L, TK, *cur, *nxt, g, w, w0, part, stream));
             if (norm) *norm_parts = TK.count();
+        } else if (k > 1 && !norm && cj::sweepk_supported(p->s.stencil, (int)k, L.elem_bytes)) {
+            const cj::Tiles Tk = cj::make_tiles_k(L.nx, L.ny, (int)k, radius(p->s.stencil), p->opt.tile_rows);
+            CJ_HIP(cj::launch_sweepk(p->s.stencil, (int)k, L, Tk, *cur, *nxt, g, w, w0, nullptr, stream));
         } else {
             k = 1;
             CJ_HIP(cj::launch_sweep(p->s.stencil, L, p->T, *cur, *nxt, g, w, w0, part, stream));
@@ -453,7 +457,7 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol, const cj_o
     const int elem = mixed ? 4 : 8;
     if (o.sweeps_per_launch > 1 && !cj::sweepk_supported(stencil, o.sweeps_per_launch, elem))
         return fail(CJ_ERR_ARG, "sweeps_per_launch not available for this stencil and precision "
-                                "(FP64: 5/9-point 1, 2, 3, 4, 6, 8, 17-point 1, 2, 3, 4; "
+                                "(FP64: 5/9-point 1, 2, 3, 4, 6, 8, 10, 17-point 1, 2, 3, 4; "
                                 "FP32: 5/9-point 1, 2, 4, 8, 17-point 1, 2, 3, 4)");
     if (!mixed && o.inner_M != 0) return fail(CJ_ERR_ARG, "inner_M applies to CJ_PRECISION_F32_REFINE plans only");
     cj_plan_s* p = new (std::nothrow) cj_plan_s();
@@ -484,8 +488,11 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol, const cj_o
     const int R = radius(stencil);
     const int frame = bc == CJ_BC_DIRICHLET_FRAME ? R : 0;
     p->L = cj::make_layout(nx, ny, 8, frame);
-    // default depths from measurements at 8192^2 on MI355X (9-point FP64: K = 8 is
-    // 3.2x the single-sweep rate; 17-point: K = 3, deeper windows exhaust the registers)
+    // default depths from measurements at 8192^2 on MI355X: FP64 9-point K = 10
+    // (68.6 us per sweep; K = 8: 70.1) on grids above 2^22 points, K = 8 on
+    // smaller ones, where a cycle of whole K-launches replays as one graph;
+    // 5-point K = 8; 17-point K = 4 (152.5 us per sweep; K = 5 no longer fits
+    // two waves per SIMD).  FP32: K = 8, 17-point K = 4.
     if (mixed) {
         // the corrections have zero boundary data in the same frame geometry
         p->L32 = cj::make_layout(nx, ny, 4, frame);
@@ -494,7 +501,8 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol, const cj_o
         p->T = cj::make_tiles(nx, ny, p->K32 == 1 ? o.tile_rows : 0);
         if (p->K32 > 1) p->TK32 = cj::make_tiles_k(nx, ny, p->K32, R, o.tile_rows);
     } else {
-        p->K = o.sweeps_per_launch > 0 ? o.sweeps_per_launch : (stencil == 17 ? 3 : 8);
+        const bool large = (long long)nx * ny > (1LL << 22);
+        p->K = o.sweeps_per_launch > 0 ? o.sweeps_per_launch : (stencil == 17 ? 4 : (stencil == 9 && large) ? 10 : 8);
         p->T = cj::make_tiles(nx, ny, p->K == 1 ? o.tile_rows : 0);
         if (p->K > 1) p->TK = cj::make_tiles_k(nx, ny, p->K, R, o.tile_rows);
     }

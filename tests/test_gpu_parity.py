@@ -100,7 +100,9 @@ def test_sweep_prefix_from_rough_guess(torch_cuda, st):
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
-BLOCKED = [(5, 2), (5, 3), (5, 4), (5, 6), (5, 8), (9, 2), (9, 3), (9, 4), (9, 6), (9, 8),
+# with M = 8 below, K = 6 and K = 10 also exercise the shorter blocked launch
+# that finishes a cycle (2 and 8 sweeps)
+BLOCKED = [(5, 2), (5, 3), (5, 4), (5, 6), (5, 8), (5, 10), (9, 2), (9, 3), (9, 4), (9, 6), (9, 8), (9, 10),
            (17, 2), (17, 3), (17, 4)]
 
 
@@ -125,7 +127,7 @@ def test_blocked_sweeps_match_single_sweeps_bitwise(torch_cuda, st, K, nx, ny, r
     assert np.abs(_host(uk) - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("st,K", [(9, 1), (9, 8), (5, 1), (17, 1), (17, 4)])
+@pytest.mark.parametrize("st,K", [(9, 1), (9, 8), (9, 10), (5, 1), (17, 1), (17, 4)])
 def test_full_solve_parity_launch_depths(torch_cuda, st, K):
     torch = torch_cuda
     nx, ny, tol = 211, 143, 1e-10
