@@ -45,18 +45,19 @@ def kernel_hash():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic(n, stencil):
+def measured_traffic(n, stencil, K, rows):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary, or
-    None when there is none or the kernel source changed since it was taken."""
+    None when there is none, the kernel source changed since it was taken, or it
+    was taken for another launch geometry (K, tile rows)."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     text = open(TRAFFIC_FILE).read()
     m = re.search(r"kernels\.hip sha256\[:16\]:\s*([0-9a-f]{16})", text)
     t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    w = re.search(r"workload:\s*n=(\d+)\s+stencil=(\d+)", text)
+    w = re.search(r"workload:\s*n=(\d+)\s+stencil=(\d+)\s+K=(\d+)\s+rows=(\d+)", text)
     if not (m and t and w) or m.group(1) != kernel_hash():
         return None
-    if int(w.group(1)) != n or int(w.group(2)) != stencil:
+    if tuple(int(v) for v in w.groups()) != (n, stencil, K, rows):
         return None
     return float(t.group(1))
 
@@ -82,7 +83,7 @@ def single_sweep_reference(cj, fd, n, st, tol, launches=48):
             "achieved": round(achieved, 1), "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
 
 
-def traffic_probe(n, st, tol, launches=4):
+def traffic_probe(n, st, tol, rows=0, launches=4):
     """Short run for rocprofv3 counter passes: a plain copy of known size (for the
     counter calibration) and a few launches of each sweep kernel."""
     import torch
@@ -93,13 +94,13 @@ def traffic_probe(n, st, tol, launches=4):
         b.copy_(a)
     fd = torch.from_numpy(inputs.gaussian_bumps_rhs(n, n, seed=1705 + st)).to("cuda")
     u = torch.zeros_like(fd)
-    pk = cj.plan(n, n, st, tol)
+    pk = cj.plan(n, n, st, tol, tile_rows=rows)
     cj.sweeps(pk, fd, u, launches * pk.sweeps_per_launch)
     p1 = cj.plan(n, n, st, tol, sweeps_per_launch=1)
     cj.sweeps(p1, fd, u, launches)
     torch.cuda.synchronize()
     print(json.dumps({"probe": "traffic", "copy_bytes_each": 2 * a.numel() * 8, "copies": 3, "n": n,
-                      "stencil": st, "K": pk.sweeps_per_launch, "blocked_launches": launches,
+                      "stencil": st, "K": pk.sweeps_per_launch, "rows": pk.tile_rows, "blocked_launches": launches,
                       "single_launches": launches}), flush=True)
 
 
@@ -463,6 +464,8 @@ def main():
     ap.add_argument("--seed", type=int, default=None, help="RHS seed (default 1705 + stencil)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile-rows", type=int, default=0,
+                    help="traffic probe: tile height of the blocked launches (0: the plan's default)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run only the short copy + sweep probe used for rocprofv3 counter passes")
     ap.add_argument("--workload", choices=("single", "batch", "serve", "paper"), default="single",
@@ -507,7 +510,7 @@ def main():
     n, st, tol = args.n, args.stencil, args.tol
     ny = args.n if args.ny is None else args.ny
     if args.traffic_probe:
-        traffic_probe(n, st, tol)
+        traffic_probe(n, st, tol, rows=args.tile_rows)
         return
     mixed = args.precision == "f32-refine"
     seed = 1705 + st if args.seed is None else args.seed
@@ -520,6 +523,7 @@ def main():
         u.zero_()
         cj.solve(p, fd, u)
     torch.cuda.synchronize()
+    p.refresh_launch_info()     # the tile height the first solve chose on the device
 
     lat, res = [], []
     t0 = time.perf_counter()
@@ -546,7 +550,7 @@ def main():
         avg = sweep_s / launches
         algo = bpu * K * n * ny
         achieved = algo / avg / 1e9
-        traffic = None if (mixed or ny != n) else measured_traffic(n, st)
+        traffic = None if (mixed or ny != n) else measured_traffic(n, st, K, p.tile_rows)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "kernel": "sweepk_kernel<%s, %d, K=%d, no-norm>" % ("float" if mixed else "double", st, K),

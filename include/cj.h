@@ -107,7 +107,10 @@ typedef struct {
                                   FP32: 8, 17-point 4); FP64 1, 2, 3, 4, 6, 8, 10
                                   (5/9-point) or 1, 2, 3, 4 (17-point); FP32 1, 2, 4, 8
                                   (5/9-point) or 1, 2, 3, 4 (17-point) */
-    int    tile_rows;          /* rows per workgroup tile of the sweep kernel, 0 = auto */
+    int    tile_rows;          /* rows per workgroup tile of the sweep kernel; 0 = automatic:
+                                  on grids of more than 2^22 points the first cj_solve times
+                                  the blocked kernel at several heights on the device and
+                                  keeps the fastest (results do not depend on it) */
     double h;                  /* mesh spacing; 0 = 1 / max(nx + 1, ny + 1) */
     int    precision;          /* cj_precision; 0 = CJ_PRECISION_F64 */
     int    inner_M;            /* CJ_PRECISION_F32_REFINE: inner cycle length (a power of

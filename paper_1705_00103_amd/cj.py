@@ -184,10 +184,16 @@ class Plan:
         self.kmin, self.kmax, self.M, self.cycles_pred = kmin.value, kmax.value, Mo.value, cp.value
         self.weights = [w[k] for k in range(self.M)]
         self.workspace_bytes = ws.value
+        self.refresh_launch_info()
+
+    def refresh_launch_info(self):
+        """Re-reads cj_plan_launch_info (the tile height of large grids is chosen
+        on the device at the first solve)."""
         k, rows, wg = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        _check(L.cj_plan_launch_info(handle, ctypes.byref(k), ctypes.byref(rows), ctypes.byref(wg)),
+        _check(lib().cj_plan_launch_info(self.handle, ctypes.byref(k), ctypes.byref(rows), ctypes.byref(wg)),
                "cj_plan_launch_info")
         self.sweeps_per_launch, self.tile_rows, self.workgroups = k.value, rows.value, wg.value
+        return self.sweeps_per_launch, self.tile_rows, self.workgroups
 
     @property
     def handle(self):

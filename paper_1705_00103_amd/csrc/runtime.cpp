@@ -98,6 +98,10 @@ struct cj_plan_s {
     // The plain launches of an FP64 cycle (all but the first, norm-fused one),
     // captured once as a graph on a private stream and replayed every cycle.
     bool use_graph = false;
+    // Tile height of the blocked kernels: chosen on the device at the first
+    // solve (tune_rows) unless the options fix it.
+    bool tune_rows = false;
+    bool rows_tuned = false;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -112,8 +116,14 @@ struct cj_plan_s {
     int n_partials() const {
         int n = T.count();
         if (TK.count() > n) n = TK.count();
+        if (tune_rows && K > 1) {
+            // room for the flattest tile the tuner may choose
+            const int m = cj::make_tiles_k(s.nx, s.ny, K, s.stencil == 17 ? 2 : 1, kTuneRows[0]).count();
+            if (m > n) n = m;
+        }
         return n;
     }
+    static constexpr int kTuneRows[6] = {64, 96, 128, 160, 192, 256};
 };
 
 namespace {
@@ -291,6 +301,49 @@ cj_status capture_cycle(cj_plan_s* p, long long k0) {
     CJ_HIP(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
     p->graph_launches = launches;
     if (cur != p->A) return fail(CJ_ERR_HIP, "captured cycle does not end in the start buffer");
+    return CJ_OK;
+}
+
+// Tile-height tuner of the blocked kernels (FP64 plans: TK, refinement plans:
+// TK32).  Each candidate height runs one warm-up launch and one timed launch
+// of K sweeps from the first iterate buffer into the second (the FP64 plan
+// reads A, whose iterate stays intact, and writes B, which the solve
+// overwrites before reading; refinement plans use the correction buffers,
+// which the solve resets).  The fastest height is kept for the life of the
+// plan.  Every tile geometry gives the same bits, so this changes speed only.
+cj_status tune_tile_rows(cj_plan_s* p, hipStream_t stream) {
+    if (!p->tune_rows || p->rows_tuned) return CJ_OK;
+    p->rows_tuned = true;
+    const bool mixed = p->mixed();
+    const int K = mixed ? p->K32 : p->K;
+    if (K <= 1) return CJ_OK;
+    const int R = radius(p->s.stencil);
+    cj::Tiles best = mixed ? p->TK32 : p->TK;
+    float best_ms = -1.0f;
+    for (int rows : cj_plan_s::kTuneRows) {
+        if (rows > p->s.ny) break;
+        const cj::Tiles Tc = cj::make_tiles_k(p->s.nx, p->s.ny, K, R, rows);
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2; ++rep) {
+            CJ_HIP(hipEventRecord(p->ev[0], stream));
+            if (mixed)
+                CJ_HIP(cj::launch_sweepk(p->s.stencil, K, p->L32, Tc, p->D1, p->D2, p->R32, p->W32, 0, nullptr,
+                                         stream));
+            else
+                CJ_HIP(cj::launch_sweepk(p->s.stencil, K, p->L, Tc, p->A, p->B, p->G, p->W, 0, nullptr, stream));
+            CJ_HIP(hipEventRecord(p->ev[1], stream));
+            CJ_HIP(hipEventSynchronize(p->ev[1]));
+            CJ_HIP(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
+        }
+        if (best_ms < 0.0f || ms < best_ms) {
+            best_ms = ms;
+            best = Tc;
+        }
+    }
+    if (mixed)
+        p->TK32 = best;
+    else
+        p->TK = best;
     return CJ_OK;
 }
 
@@ -507,6 +560,9 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol, const cj_o
         if (p->K > 1) p->TK = cj::make_tiles_k(nx, ny, p->K, R, o.tile_rows);
     }
     p->D = centre_over_s(stencil) / (p->s.h * p->s.h);
+    // large grids: the tile height that fills the device best is measured
+    // (it depends on how many workgroups fit per CU and on the grid)
+    p->tune_rows = o.tile_rows == 0 && (long long)nx * ny > (1LL << 22) && (mixed ? p->K32 : p->K) > 1;
     if (o.graph < -1 || o.graph > 1) {
         delete p;
         return fail(CJ_ERR_ARG, "graph must be -1, 0 or 1");
@@ -579,6 +635,7 @@ cj_status cj_solve(cj_plan_t p, const double* f, double* u, void* stream_, cj_re
     const double gnorm = std::sqrt(g2);
     double* answer = p->A;
     cj_status outcome;
+    if ((st = tune_tile_rows(p, stream)) != CJ_OK) return finish(st);
     if (p->mixed())
         outcome = solve_refine(p, gnorm, stream, &r);
     else

@@ -4,6 +4,7 @@ Bar (FP64 path): relative L2 difference <= 1e-12 on the same inputs and the same
 weight schedule; statuses and cycle counts identical.  Inputs come from
 paper_1705_00103_amd.inputs; expected values from oracle/ only.
 """
+import ctypes
 import math
 import sys
 
@@ -281,3 +282,26 @@ def test_graph_replayed_cycles_match_eager_launches(torch_cuda, st, nx, ny):
         if ref is None:
             ref = ue.clone()
         assert torch.equal(ug, ref)
+
+
+@pytest.mark.parametrize("st,precision", [(9, cj.F64), (17, cj.F64), (9, cj.F32_REFINE)])
+def test_tuned_tile_height_gives_the_same_bits(torch_cuda, st, precision):
+    """Grids above 2^22 points pick the blocked kernels' tile height on the
+    device at the first solve; the result is bit-identical to a fixed height."""
+    torch = torch_cuda
+    nx, ny, tol = 2100, 2050, 1e-6
+    f = _dev(torch, inputs.gaussian_bumps_rhs(nx, ny, seed=5))
+    p_auto = cj.plan(nx, ny, st, tol, precision=precision)
+    p_fix = cj.plan(nx, ny, st, tol, precision=precision, tile_rows=128)
+    ua = torch.zeros(ny, nx, dtype=torch.float64, device="cuda")
+    uf = torch.zeros_like(ua)
+    ra = cj.solve(p_auto, f, ua)
+    rf = cj.solve(p_fix, f, uf)
+    L = cj.lib()
+    rows = ctypes.c_int()
+    assert L.cj_plan_launch_info(p_auto.handle, None, ctypes.byref(rows), None) == 0
+    print("st %d precision %d: tuned rows %d, %s / %s" % (st, precision, rows.value, ra["status"], rf["status"]),
+          flush=True)
+    assert rows.value in (64, 96, 128, 160, 192, 256)
+    assert (ra["status"], ra["cycles"]) == (rf["status"], rf["cycles"])
+    assert torch.equal(ua, uf)
