@@ -472,7 +472,8 @@ def main():
                     help="single: one large solve (default); batch: many uneven problems in shared launches; "
                          "serve: Poisson arrivals into the continuous-batching server")
     ap.add_argument("--serve-n", type=int, default=160, help="serve: number of requests")
-    ap.add_argument("--serve-rate", type=float, default=20.0, help="serve: arrivals per second")
+    ap.add_argument("--serve-rate", type=float, default=60.0,
+                    help="serve: arrivals per second (60/s is above what one-at-a-time FP64 solves sustain)")
     ap.add_argument("--serve-lo", type=int, default=64)
     ap.add_argument("--serve-hi", type=int, default=4096)
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
