@@ -74,6 +74,8 @@ def test_plan_explicit_M_and_options():
     ((5, 5, 9, 1e-8), {"M": -2}), ((5, 5, 9, 1e-8), {"bc": 2}), ((5, 5, 9, 1e-8), {"max_cycles": -1}),
     ((5, 5, 9, 1e-8), {"h": -0.5}), ((5, 5, 9, 1e-8), {"method": 2}),
     ((5, 5, 9, 1e-8), {"method": 1, "precision": 1}), ((5, 5, 9, 1e-8), {"method": 1, "M": 3}),
+    (((1 << 20) + 1, 5, 9, 1e-8), {}), ((5, (1 << 20) + 1, 17, 1e-8), {}), ((5, 5, 9, float("inf")), {}),
+    ((5, 5, 9, 1e-8), {"sweeps_per_launch": 5}), ((5, 5, 17, 1e-8), {"sweeps_per_launch": 6}),
 ])
 def test_plan_rejects_bad_arguments(args, kw):
     with pytest.raises(cj.CJError) as e:

@@ -305,3 +305,24 @@ def test_tuned_tile_height_gives_the_same_bits(torch_cuda, st, precision):
     assert rows.value in (64, 96, 128, 160, 192, 256)
     assert (ra["status"], ra["cycles"]) == (rf["status"], rf["cycles"])
     assert torch.equal(ua, uf)
+
+
+@pytest.mark.parametrize("st", [5, 9, 17])
+@pytest.mark.parametrize("nx,ny", [(1 << 20, 2), (3, 1 << 17), (70001, 5)])
+def test_extreme_aspect_ratios(torch_cuda, st, nx, ny):
+    """The largest axis the planner accepts (2^20 nodes), long thin strips and
+    single-tile widths: blocked sweeps still match the oracle and the single sweep."""
+    torch = torch_cuda
+    n = 13
+    f = inputs.random_field(nx, ny, seed=3)
+    u0 = inputs.random_field(nx, ny, seed=4)
+    ref = cjm.run_sweeps(f, nx, ny, st, 1e-6, n, M=16, u0=u0)
+    outs = []
+    for K in (1, 0):
+        p = cj.plan(nx, ny, st, 1e-6, M=16, sweeps_per_launch=K)
+        u = _dev(torch, u0)
+        cj.sweeps(p, _dev(torch, f), u, n)
+        outs.append(_host(u))
+        p.destroy()
+    assert np.array_equal(outs[0], outs[1])
+    assert np.abs(outs[0] - ref).max() <= 1e-12 * np.abs(ref).max()

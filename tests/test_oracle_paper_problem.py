@@ -152,3 +152,17 @@ def test_jacobi_and_cjm_reach_the_same_solution(st):
     assert rj["status"] == "ok" and rc["status"] == "ok"
     assert rj["sweeps"] > 5 * rc["sweeps"]
     assert np.abs(rj["u"] - rc["u"]).max() < 1e-9
+
+
+@pytest.mark.parametrize("st", STENCILS)
+def test_frame_apply_is_minus_laplacian_of_a_cubic(st):
+    """A u with u's frame as data: on a cubic every stencil here is exact, so
+    A p = -Delta p at every interior node."""
+    nx, ny = 19, 12
+    G = inputs.frame_width(st)
+    x, y = inputs.coords(nx, ny)
+    X, Y = np.meshgrid(x, y)
+    frame = inputs.frame_from_function(_poly, nx, ny, G, interior=_poly(X, Y))
+    au = cjm.apply(st, frame, nx, ny, bc=cjm.BC_FRAME)
+    want = -_lap_poly(X, Y)
+    assert np.abs(au - want).max() <= 1e-9 * np.abs(want).max()
