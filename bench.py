@@ -41,8 +41,14 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweepk9_f64_8192_traffic.md")
 
 
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """sha256[:16] of kernels.hip with comments and whitespace removed: a change
+    of the code, not of its comments, invalidates a stored counter summary."""
+    with open(KERNEL_SRC) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    text = " ".join(text.split())
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
 def measured_traffic(n, stencil, K, rows):
@@ -52,7 +58,7 @@ def measured_traffic(n, stencil, K, rows):
     if not os.path.exists(TRAFFIC_FILE):
         return None
     text = open(TRAFFIC_FILE).read()
-    m = re.search(r"kernels\.hip sha256\[:16\]:\s*([0-9a-f]{16})", text)
+    m = re.search(r"kernels\.hip sha256\[:16\][^:\n]*:\s*([0-9a-f]{16})", text)
     t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
     w = re.search(r"workload:\s*n=(\d+)\s+stencil=(\d+)\s+K=(\d+)\s+rows=(\d+)", text)
     if not (m and t and w) or m.group(1) != kernel_hash():

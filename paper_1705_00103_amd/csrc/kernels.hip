@@ -4,13 +4,15 @@
 // FP64 pieces of iterative refinement.
 //
 // All kernels work on the padded, pitched layout described in cj_internal.h.
-// A sweep is HBM-bound (24 bytes in FP64, 12 in FP32, and 8-24 flops per
-// grid-point update), so the kernels are organised around memory traffic: one
-// wave64 lane per grid column, marching up the rows of its tile and keeping
-// the (2R+1) rows of the stencil window in registers, so that every value of
-// u is fetched from HBM once per sweep and the row re-reads of the window hit
-// registers.  Row loads of a wave are 64 consecutive elements, aligned on the
-// interior.
+// A single sweep is HBM-bound (24 bytes in FP64, 12 in FP32, and 8-16 flops
+// per grid-point update), so the kernels are organised around memory
+// traffic: one wave64 lane per grid column, marching up the rows of its tile
+// and keeping the (2R+1) rows of the stencil window in registers, so that
+// every value of u is fetched from HBM once per sweep and the row re-reads of
+// the window hit registers.  Row loads of a wave are 64 consecutive elements,
+// aligned on the interior.  The temporally blocked kernel performs K updates
+// per HBM pass; it is bound by FP64 latency, instruction issue and its LDS
+// exchange instead.
 //
 // Arithmetic is written with explicit fma and compiled with
 // -ffp-contract=off, so that every kernel that evaluates the update in a
@@ -220,15 +222,15 @@ __global__ __launch_bounds__(256) void sweep_kernel(const T* __restrict__ uin, T
 // x +- R neighbours), levels 1..K-1 are exchanged between lanes through LDS,
 // and every lane keeps a register window of 2R+1 row summaries per level
 // (see Stencil), each row tagged with the lane's value of g on that row (the
-// g a level used for a row is the g the next level needs on it).  Only level K is written back, so one
-// launch moves one read of u and g and one write of u per grid point and
-// performs K updates per point.
+// g a level used for a row is the g the next level needs on it).  Only level
+// K is written back, so one launch moves one read of u and g and one write of
+// u per grid point and performs K updates per point.
 // Outputs shrink by R columns per level on each side of the strip
 // (256 - 2KR output columns) and the tiles overlap in y by KR rows.
 // The row loop is unrolled by a multiple of the window height W = 2R+1 (and
 // of the prefetch depth) so that the window rotation is a compile-time
-// renaming of registers.  Workgroups whose halo
-// reaches the domain boundary take a variant that closes the levels >= 1:
+// renaming of registers.  Workgroups whose halo reaches the domain boundary
+// take a variant that closes the levels >= 1:
 // with REFL (17-point, homogeneous data) by the Dirichlet zeros and the odd
 // reflections of the level below; otherwise every node outside the interior
 // keeps, at every level, the value level 0 loaded for it (the boundary data).
@@ -259,7 +261,7 @@ struct March {
     static constexpr int NV = R + 1;
     T win[K][W][NV];      // [level][physical row slot][row summary]
     T gw[K][W];       // g of the lane's column on each window row
-    T own[K];         // the lane's value of the row a level produced in this step
+    T own[K];         // the lane's value on the row a level produced in this step
     T gused[K];       // the g it used
     T pre[PD][W];     // prefetched level-0 rows
     T pg[PD];         // and their g
