@@ -263,8 +263,9 @@ cj_status cj_server_create(const cj_options* opt, size_t hbm_budget_bytes, void*
 cj_status cj_server_submit(cj_server_t s, int nx, int ny, int stencil, double tol, const double* f, double* u,
                            long long* ticket);
 
-/* Admits what fits, advances every admitted request by one batched launch
- * (with cycle-end work where due) and reports up to max_done finished
+/* Admits what fits, advances every admitted request by batched launches up
+ * to the first inner-cycle end among them (at most 32 launches of K sweeps),
+ * does the cycle-end work that is due, and reports up to max_done finished
  * requests (tickets and results; results[].seconds is the time from submit
  * to completion).  *n_done receives their number. */
 cj_status cj_server_step(cj_server_t s, long long* done_tickets, cj_result* done_results, int max_done,

@@ -9,7 +9,9 @@
 // Engine step (one "super-step"):
 //   1. admit queued problems that fit: allocate, stage u and g = D^{-1} f in;
 //   2. one launch per stencil group runs K FP32 sweeps of every active problem
-//      (one workgroup per (problem, tile) work item);
+//      (one workgroup per (problem, tile) work item), repeated up to the first
+//      inner-cycle end among the active problems (the server: at most 32
+//      times, so that arrivals are admitted soon);
 //   3. problems whose inner cycle ended (set E), and the newly admitted ones,
 //      get their correction u += d and their next FP64 residual (rounded to
 //      FP32, plus per-tile partial norms) in batched launches; one segmented
@@ -222,6 +224,11 @@ public:
     double* part = nullptr;
     size_t part_cap = 0;
     int step_no = 0;
+    // Most super-steps one engine step enqueues (0: no limit).  A step runs up
+    // to the first inner-cycle end among the active problems, where the host
+    // has something to decide; the server caps it so that new arrivals are
+    // admitted soon, a batch (all problems known up front) does not.
+    int max_supersteps = 0;
     bool rebuild = true;
     size_t group_size[3] = {0, 0, 0};
     long long launches = 0, supersteps = 0;
@@ -410,6 +417,7 @@ public:
             }
         }
         // batched sweeps of the active problems
+        int n_ss = 0;
         bool any_active = false;
         for (Problem* p : live) any_active = any_active || p->state == State::Active;
         if (any_active) {
@@ -433,28 +441,40 @@ public:
                 CJB_HIP(hipStreamSynchronize(stream));
                 rebuild = false;
             }
-            size_t base = 0;
-            for (int gi = 0; gi < 3; ++gi) {
-                if (group_size[gi] == 0) continue;
-                int K = 0;
+            // super-steps until the first cycle end among the active problems
+            n_ss = 0;
+            for (Problem* p : live)
+                if (p->state == State::Active) {
+                    const int left = p->m / p->K - p->j;
+                    if (n_ss == 0 || left < n_ss) n_ss = left;
+                }
+            if (n_ss < 1) n_ss = 1;
+            if (max_supersteps > 0 && n_ss > max_supersteps) n_ss = max_supersteps;
+            int Kg[3] = {0, 0, 0};
+            for (int gi = 0; gi < 3; ++gi)
                 for (Problem* p : live)
                     if (p->state == State::Active && p->stencil == kStencils[gi]) {
-                        K = p->K;
+                        Kg[gi] = p->K;   // one depth per stencil group
                         break;
                     }
-                CJB_HIP(cj::launch_batch_sweepk(kStencils[gi], K, probs.d, work.d + base, (int)group_size[gi],
-                                                step_no, stream));
-                ++launches;
-                base += group_size[gi];
+            for (int k = 0; k < n_ss; ++k) {
+                size_t base = 0;
+                for (int gi = 0; gi < 3; ++gi) {
+                    if (group_size[gi] == 0) continue;
+                    CJB_HIP(cj::launch_batch_sweepk(kStencils[gi], Kg[gi], probs.d, work.d + base,
+                                                    (int)group_size[gi], step_no, stream));
+                    ++launches;
+                    base += group_size[gi];
+                }
+                ++step_no;
+                ++supersteps;
             }
-            ++step_no;
-            ++supersteps;
         }
         // cycle ends
         std::vector<Problem*> R;
         for (Problem* p : live) {
             if (p->state != State::Active) continue;
-            ++p->j;
+            p->j += n_ss;
             if (p->j * p->K == p->m) {
                 R.push_back(p);
                 p->sweeps += p->m;
@@ -746,6 +766,7 @@ cj_status cj_server_create(const cj_options* opt, size_t hbm_budget_bytes, void*
     s->eng.Kreq = Kreq;
     s->eng.max_outer = o.max_cycles > 0 ? o.max_cycles : 50;
     s->eng.budget = align256(hbm_budget_bytes);
+    s->eng.max_supersteps = 32;   // admissions wait at most this many super-steps
     s->stream = static_cast<hipStream_t>(stream);
     *out = s;
     return CJ_OK;
