@@ -422,6 +422,29 @@ public:
         for (Problem* p : live) any_active = any_active || p->state == State::Active;
         if (any_active) {
             if (rebuild) {
+                if (opt.tile_rows == 0) {
+                    // Tile height from the load: 64 rows while the active problems
+                    // have at least 2048 tiles (the device is full and taller tiles
+                    // waste less on their pipeline fill), shorter (down to 16) when
+                    // few problems run, so that a lone small problem still spreads
+                    // over many CUs.  Tiles only partition the grid: results do not
+                    // depend on the height.
+                    int rows = 64;
+                    for (; rows > 16; rows /= 2) {
+                        long long tiles = 0;
+                        for (Problem* p : live)
+                            if (p->state == State::Active)
+                                tiles += cj::make_tiles_k(p->nx, p->ny, p->K, p->stencil == 17 ? 2 : 1, rows).count();
+                        if (tiles >= 2048) break;
+                    }
+                    for (Problem* p : live)
+                        if (p->state == State::Active && p->TK.rows != std::min(rows, p->ny)) {
+                            p->TK = cj::make_tiles_k(p->nx, p->ny, p->K, p->stencil == 17 ? 2 : 1, rows);
+                            desc(p).strips_x = p->TK.tiles_x;
+                            desc(p).rows_k = p->TK.rows;
+                        }
+                    if ((st = upload_probs(stream)) != CJ_OK) return st;
+                }
                 size_t n = 0;
                 for (Problem* p : live)
                     if (p->state == State::Active) n += p->TK.count();
