@@ -130,6 +130,9 @@ hipError_t launch_sweep(int stencil, const Layout& L, const Tiles& T, const floa
 bool sweepk_supported(int stencil, int K, int elem_bytes);
 hipError_t launch_sweepk(int stencil, int K, const Layout& L, const Tiles& T, const double* uin, double* uout,
                          const double* g, const double* w, int widx, double* part, hipStream_t stream);
+// Workgroups of the blocked kernel (stencil, K, element size, 17-point
+// reflection) resident per CU at once, from the HIP occupancy calculator.
+hipError_t sweepk_blocks_per_cu(int stencil, int K, int elem_bytes, bool refl, int* blocks);
 // The same in FP32 (part must be nullptr).
 hipError_t launch_sweepk(int stencil, int K, const Layout& L, const Tiles& T, const float* uin, float* uout,
                          const float* g, const float* w, int widx, double* part, hipStream_t stream);

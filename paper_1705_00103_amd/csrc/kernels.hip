@@ -887,6 +887,35 @@ hipError_t launch_sweepk(int stencil, int K, const Layout& L, const Tiles& Tl, c
     return hipErrorInvalidValue;
 }
 
+namespace {
+template <typename T, int ST, int K>
+hipError_t occupancy_k(bool refl, int* blocks) {
+    if (ST == 17 && refl)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweepk_kernel<T, ST, K, false, true>, 256, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweepk_kernel<T, ST, K, false, false>, 256, 0);
+}
+}  // namespace
+
+hipError_t sweepk_blocks_per_cu(int stencil, int K, int elem_bytes, bool refl, int* blocks) {
+    *blocks = 0;
+    if (elem_bytes == 8) {
+#define CJ_K_CASE(ST, KK) \
+        if (stencil == ST && K == KK) return occupancy_k<double, ST, KK>(refl, blocks);
+        CJ_K_CASE(5, 2) CJ_K_CASE(5, 3) CJ_K_CASE(5, 4) CJ_K_CASE(5, 6) CJ_K_CASE(5, 8)
+        CJ_K_CASE(9, 2) CJ_K_CASE(9, 3) CJ_K_CASE(9, 4) CJ_K_CASE(9, 6) CJ_K_CASE(9, 8) CJ_K_CASE(9, 10)
+        CJ_K_CASE(5, 10) CJ_K_CASE(17, 2) CJ_K_CASE(17, 3) CJ_K_CASE(17, 4)
+#undef CJ_K_CASE
+    } else {
+#define CJ_K_CASE(ST, KK) \
+        if (stencil == ST && K == KK) return occupancy_k<float, ST, KK>(refl, blocks);
+        CJ_K_CASE(5, 2) CJ_K_CASE(5, 4) CJ_K_CASE(5, 8)
+        CJ_K_CASE(9, 2) CJ_K_CASE(9, 4) CJ_K_CASE(9, 8)
+        CJ_K_CASE(17, 2) CJ_K_CASE(17, 3) CJ_K_CASE(17, 4)
+#undef CJ_K_CASE
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_residual(int stencil, const Layout& L, const Tiles& T, const double* u, const double* g,
                            double* part, hipStream_t stream) {
     switch (stencil) {

@@ -19,7 +19,9 @@
 // residual meets tol.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
+#include <iterator>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -305,7 +307,9 @@ cj_status capture_cycle(cj_plan_s* p, long long k0) {
 }
 
 // Tile-height tuner of the blocked kernels (FP64 plans: TK, refinement plans:
-// TK32).  Each candidate height runs one warm-up launch and one timed launch
+// TK32).  Candidates: 64 .. 256 rows, and the heights that make the tile count
+// fill whole rounds of the workgroups the device holds at once (the launch
+// then has no partly idle last round).  Each candidate runs one warm-up launch and one timed launch
 // of K sweeps from the first iterate buffer into the second (the FP64 plan
 // reads A, whose iterate stays intact, and writes B, which the solve
 // overwrites before reading; refinement plans use the correction buffers,
@@ -318,11 +322,35 @@ cj_status tune_tile_rows(cj_plan_s* p, hipStream_t stream) {
     const int K = mixed ? p->K32 : p->K;
     if (K <= 1) return CJ_OK;
     const int R = radius(p->s.stencil);
+    const int nx = p->s.nx, ny = p->s.ny;
+    // candidates: a fixed ladder, plus the heights whose tile count just fills
+    // r rounds of the workgroups the device holds at once (r = 1 .. 8)
+    std::vector<int> cand(std::begin(cj_plan_s::kTuneRows), std::end(cj_plan_s::kTuneRows));
+    {
+        const cj::Layout& Lk = mixed ? p->L32 : p->L;
+        int per_cu = 0, cus = 0;
+        const bool refl = p->s.stencil == 17 && Lk.frame == 0;
+        if (cj::sweepk_blocks_per_cu(p->s.stencil, K, Lk.elem_bytes, refl, &per_cu) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess &&
+            per_cu > 0 && cus > 0) {
+            const long long slots = (long long)per_cu * cus;
+            const int strips = cj::make_tiles_k(nx, ny, K, R, cj_plan_s::kTuneRows[0]).tiles_x;
+            for (int r = 1; r <= 8; ++r) {
+                const long long ty = r * slots / strips;
+                if (ty < 1) continue;
+                const long long rows = (ny + ty - 1) / ty;
+                if (rows >= cj_plan_s::kTuneRows[0] && rows <= 2048) cand.push_back((int)rows);
+            }
+        }
+        (void)hipGetLastError();
+        std::sort(cand.begin(), cand.end());
+        cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+    }
     cj::Tiles best = mixed ? p->TK32 : p->TK;
     float best_ms = -1.0f;
-    for (int rows : cj_plan_s::kTuneRows) {
-        if (rows > p->s.ny) break;
-        const cj::Tiles Tc = cj::make_tiles_k(p->s.nx, p->s.ny, K, R, rows);
+    for (int rows : cand) {
+        if (rows > ny) break;
+        const cj::Tiles Tc = cj::make_tiles_k(nx, ny, K, R, rows);
         float ms = 0.0f;
         for (int rep = 0; rep < 2; ++rep) {
             CJ_HIP(hipEventRecord(p->ev[0], stream));

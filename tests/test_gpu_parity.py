@@ -302,7 +302,7 @@ def test_tuned_tile_height_gives_the_same_bits(torch_cuda, st, precision):
     assert L.cj_plan_launch_info(p_auto.handle, None, ctypes.byref(rows), None) == 0
     print("st %d precision %d: tuned rows %d, %s / %s" % (st, precision, rows.value, ra["status"], rf["status"]),
           flush=True)
-    assert rows.value in (64, 96, 128, 160, 192, 256)
+    assert 64 <= rows.value <= 2048
     assert (ra["status"], ra["cycles"]) == (rf["status"], rf["cycles"])
     assert torch.equal(ua, uf)
 
