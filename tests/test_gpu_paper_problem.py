@@ -201,3 +201,20 @@ def test_frame_refined_solve(torch_cuda, st):
     u = _dev(torch, u0)
     r2 = cj.solve(p, _dev(torch, f), u)
     assert r2["status"] == "ok" and np.array_equal(_host(u), got)
+
+
+def test_frame_status_paths(torch_cuda):
+    torch = torch_cuda
+    nx, ny = 60, 45
+    for st in (9, 17):
+        G = inputs.frame_width(st)
+        f = _dev(torch, inputs.expxy_rhs(nx, ny))
+        # a NaN in the boundary data reaches the lifted right-hand side
+        bad = inputs.expxy_frame(nx, ny, G)
+        bad[0, 7] = np.nan
+        p = cj.plan(nx, ny, st, 1e-10, bc=cj.BC_FRAME)
+        assert cj.solve(p, f, _dev(torch, bad))["status"] == "nonfinite"
+        # Jacobi stopped after one check far above tol
+        pj = cj.plan(nx, ny, st, 1e-12, bc=cj.BC_FRAME, method=cj.JACOBI, M=16, max_cycles=1)
+        r = cj.solve(pj, f, _dev(torch, inputs.expxy_frame(nx, ny, G)))
+        assert r["status"] == "not_converged" and r["cycles"] == 1 and r["sweeps"] == 16
