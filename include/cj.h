@@ -164,7 +164,10 @@ cj_status cj_plan_info(cj_plan_t p, double* kmin, double* kmax, int* M, int* cyc
 
 /* Launch geometry of the plan's sweep kernel: sweeps fused per launch
  * (temporal-blocking depth K), output rows per workgroup tile and
- * workgroups per launch.  Any output pointer may be NULL. */
+ * workgroups per launch.  With tile_rows = 0 on a grid of more than 2^22
+ * points the tile height is the one the first cj_solve measured fastest;
+ * before that solve this reports the default.  Any output pointer may be
+ * NULL. */
 cj_status cj_plan_launch_info(cj_plan_t p, int* sweeps_per_launch, int* tile_rows, int* workgroups);
 
 /* Solves A u = f.  u is read as the initial guess and overwritten with the
