@@ -101,8 +101,8 @@ def test_sweep_prefix_from_rough_guess(torch_cuda, st):
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
-# with M = 8 below, K = 6 and K = 10 also exercise the shorter blocked launch
-# that finishes a cycle (2 and 8 sweeps)
+# cycles of M = 8 (K <= 8) or 32 (K = 10): K = 3, 6 and 10 also exercise the
+# shorter blocked launch that finishes a cycle
 BLOCKED = [(5, 2), (5, 3), (5, 4), (5, 6), (5, 8), (5, 10), (9, 2), (9, 3), (9, 4), (9, 6), (9, 8), (9, 10),
            (17, 2), (17, 3), (17, 4)]
 
@@ -116,15 +116,16 @@ def test_blocked_sweeps_match_single_sweeps_bitwise(torch_cuda, st, K, nx, ny, r
     torch = torch_cuda
     f = inputs.gaussian_bumps_rhs(nx, ny, seed=21)
     u0 = inputs.random_field(nx, ny, seed=22)
-    n = 2 * 8 + 3
+    M = 32 if K >= 10 else 8
+    n = 2 * M + 3
     ref1 = _dev(torch, u0)
-    cj.sweeps(cj.plan(nx, ny, st, 1e-6, M=8, sweeps_per_launch=1), _dev(torch, f), ref1, n)
-    pk = cj.plan(nx, ny, st, 1e-6, M=8, sweeps_per_launch=K, tile_rows=rows)
+    cj.sweeps(cj.plan(nx, ny, st, 1e-6, M=M, sweeps_per_launch=1), _dev(torch, f), ref1, n)
+    pk = cj.plan(nx, ny, st, 1e-6, M=M, sweeps_per_launch=K, tile_rows=rows)
     assert pk.sweeps_per_launch == K
     uk = _dev(torch, u0)
     cj.sweeps(pk, _dev(torch, f), uk, n)
     assert np.array_equal(_host(uk), _host(ref1))
-    ref = cjm.run_sweeps(f, nx, ny, st, 1e-6, n, M=8, u0=u0)
+    ref = cjm.run_sweeps(f, nx, ny, st, 1e-6, n, M=M, u0=u0)
     assert np.abs(_host(uk) - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
