@@ -102,8 +102,8 @@ typedef struct {
     int    max_cycles;         /* 0 = predicted cycles + 4 (CJ_PRECISION_F32_REFINE: the
                                   maximum number of outer steps, 0 = 50) */
     int    sweeps_per_launch;  /* temporal-blocking depth K of the sweep kernel: sweeps fused
-                                  into one launch; 0 = automatic (FP64: 9-point 10 on grids
-                                  of more than 2^22 points, else 8; 5-point 8; 17-point 4.
+                                  into one launch; 0 = automatic (FP64: 5- and 9-point 10 on
+                                  grids of more than 2^22 points, else 8; 17-point 4.
                                   FP32: 8, 17-point 4); FP64 1, 2, 3, 4, 6, 8, 10
                                   (5/9-point) or 1, 2, 3, 4 (17-point); FP32 1, 2, 4, 8
                                   (5/9-point) or 1, 2, 3, 4 (17-point) */

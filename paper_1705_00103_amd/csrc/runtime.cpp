@@ -569,11 +569,11 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol, const cj_o
     const int R = radius(stencil);
     const int frame = bc == CJ_BC_DIRICHLET_FRAME ? R : 0;
     p->L = cj::make_layout(nx, ny, 8, frame);
-    // default depths from measurements at 8192^2 on MI355X: FP64 9-point K = 10
-    // (68.6 us per sweep; K = 8: 70.1) on grids above 2^22 points, K = 8 on
-    // smaller ones, where a cycle of whole K-launches replays as one graph;
-    // 5-point K = 8; 17-point K = 4 (152.5 us per sweep; K = 5 no longer fits
-    // two waves per SIMD).  FP32: K = 8, 17-point K = 4.
+    // default depths from measurements at 8192^2 on MI355X, us per sweep: FP64
+    // 5- and 9-point K = 10 on grids above 2^22 points (9-point 60.4, K = 8: 62.6;
+    // 5-point 56.5, K = 8: 58.7), K = 8 on smaller ones, where a cycle of whole
+    // K-launches replays as one graph; 17-point K = 4 (139.1; K = 5 no longer
+    // fits two waves per SIMD).  FP32: K = 8, 17-point K = 4.
     if (mixed) {
         // the corrections have zero boundary data in the same frame geometry
         p->L32 = cj::make_layout(nx, ny, 4, frame);
@@ -583,7 +583,7 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol, const cj_o
         if (p->K32 > 1) p->TK32 = cj::make_tiles_k(nx, ny, p->K32, R, o.tile_rows);
     } else {
         const bool large = (long long)nx * ny > (1LL << 22);
-        p->K = o.sweeps_per_launch > 0 ? o.sweeps_per_launch : (stencil == 17 ? 4 : (stencil == 9 && large) ? 10 : 8);
+        p->K = o.sweeps_per_launch > 0 ? o.sweeps_per_launch : (stencil == 17 ? 4 : large ? 10 : 8);
         p->T = cj::make_tiles(nx, ny, p->K == 1 ? o.tile_rows : 0);
         if (p->K > 1) p->TK = cj::make_tiles_k(nx, ny, p->K, R, o.tile_rows);
     }

@@ -159,3 +159,11 @@ def test_frame_plans_on_the_host():
     code = L.cj_batch_create(1, (ctypes.c_int * 1)(10), (ctypes.c_int * 1)(10), (ctypes.c_int * 1)(9),
                              (ctypes.c_double * 1)(1e-8), ctypes.byref(o), ctypes.byref(h))
     assert code == cj.CJ_ERR_ARG and not h.value
+
+
+def test_default_blocking_depth():
+    """K = 10 for the 5- and 9-point stencils above 2^22 points, 8 up to it (whole
+    launches per cycle); 4 for the 17-point stencil."""
+    for st, big, small in ((5, 10, 8), (9, 10, 8), (17, 4, 4)):
+        assert cj.plan(4096, 1025, st, 1e-8).sweeps_per_launch == big
+        assert cj.plan(2048, 2048, st, 1e-8).sweeps_per_launch == small
