@@ -60,47 +60,57 @@ __device__ __forceinline__ size_t at(int pitch, int x, int y) {
 // Every coefficient multiplies a centre value or a symmetric pair of one
 // window row, so a row y + dy enters as its summary
 //     C = u(x, y + dy),  P_k = u(x - k, y + dy) + u(x + k, y + dy),  k = 1..R,
-// and t combines the summaries s[dy + R] = {C, P_1, .., P_R}:
-//     5-point : 1/4 (P_1[0] + (C[-1] + C[+1]))
-//     9-point : 1/5 (P_1[0] + (C[-1] + C[+1])) + 1/20 (P_1[-1] + P_1[+1])
-//     17-point: (64/300 (P_1[0] + (C[-1] + C[+1])) - 4/300 (P_2[0] + (C[-2] + C[+2])))
-//               + (16/300 (P_1[-1] + P_1[+1]) - 1/300 (P_2[-2] + P_2[+2])).
-// The grouping keeps the dependency chains short: the FP64 pipeline latency,
-// not the operation count, bounds the blocked kernel at two waves per SIMD.
-// The temporally blocked kernel keeps only the summaries of its window rows
-// (R + 1 values instead of 2R + 1) and forms each pair sum once per row; every
-// kernel evaluates t through these two functions, so all produce the same bits.
+// and t = scale * S, S an integer-weighted sum of the summaries
+// s[dy + R] = {C, P_1, .., P_R} (the weights differ from c_hat / scale by
+// powers of two, so scale * weight is exactly the rounded c_hat):
+//     5-point : scale 1/4,   S = P_1[0] + (C[-1] + C[+1])
+//     9-point : scale 1/20,  S = fma(4, P_1[0] + (C[-1] + C[+1]), P_1[-1] + P_1[+1])
+//     17-point: scale 1/300, S = fma(16, P_1[-1] + P_1[+1], fma(-4, P_2[0] + (C[-2] + C[+2]),
+//                                fma(64, P_1[0] + (C[-1] + C[+1]), -(P_2[-2] + P_2[+2]))))
+// and r = fma(scale, S, g) - u: the scale rides on the fma that adds g
+// (9-point: 8 FP64 operations per update with the pair sums and the update,
+// 17-point 14).  The temporally blocked kernel keeps only the summaries of its
+// window rows (R + 1 values instead of 2R + 1) and forms each pair sum once
+// per row; every kernel evaluates r through these functions, so all produce
+// the same bits.
 
 template <int ST> struct Stencil;
 
 template <> struct Stencil<5> {
     static constexpr int R = 1;
+    static constexpr double scale = 0.25;
     template <typename T> __device__ static __forceinline__ T combine(const T (&s)[3][2]) {
-        return T(0.25) * (s[1][1] + (s[0][0] + s[2][0]));
+        return s[1][1] + (s[0][0] + s[2][0]);
     }
 };
 
 template <> struct Stencil<9> {
     static constexpr int R = 1;
+    static constexpr double scale = 1.0 / 20.0;
     template <typename T> __device__ static __forceinline__ T combine(const T (&s)[3][2]) {
         const T axis = s[1][1] + (s[0][0] + s[2][0]);
         const T diag = s[0][1] + s[2][1];
-        return fmat<T>(T(0.2), axis, T(0.05) * diag);
+        return fmat<T>(T(4), axis, diag);
     }
 };
 
 template <> struct Stencil<17> {
     static constexpr int R = 2;
+    static constexpr double scale = 1.0 / 300.0;
     template <typename T> __device__ static __forceinline__ T combine(const T (&s)[5][3]) {
         const T axis1 = s[2][1] + (s[1][0] + s[3][0]);
         const T axis2 = s[2][2] + (s[0][0] + s[4][0]);
         const T diag1 = s[1][1] + s[3][1];
         const T diag2 = s[0][2] + s[4][2];
-        const T a1 = T(64.0 / 300.0), a2 = T(-4.0 / 300.0);
-        const T d1 = T(16.0 / 300.0), d2 = T(-1.0 / 300.0);
-        return fmat<T>(a1, axis1, a2 * axis2) + fmat<T>(d1, diag1, d2 * diag2);
+        return fmat<T>(T(16), diag1, fmat<T>(T(-4), axis2, fmat<T>(T(64), axis1, -diag2)));
     }
 };
+
+// r = fma(scale, S, g) - u from the window summaries, with u the centre value.
+template <typename T, int ST>
+__device__ __forceinline__ T summary_residual(const T (&s)[2 * Stencil<ST>::R + 1][Stencil<ST>::R + 1], T g, T u) {
+    return fmat<T>(T(Stencil<ST>::scale), Stencil<ST>::template combine<T>(s), g) - u;
+}
 
 // Summary {C, P_1, .., P_R} of one window row (its 2R + 1 values around x).
 template <typename T, int R>
@@ -110,14 +120,23 @@ __device__ __forceinline__ void row_summary(const T (&row)[2 * R + 1], T (&sm)[R
     for (int k = 1; k <= R; ++k) sm[k] = row[R - k] + row[R + k];
 }
 
-// t of a full window, v[dy + R][dx + R] = u(x + dx, y + dy).
+// r and t of a full window, v[dy + R][dx + R] = u(x + dx, y + dy).
+template <typename T, int ST>
+__device__ __forceinline__ T window_residual(const T (&v)[2 * Stencil<ST>::R + 1][2 * Stencil<ST>::R + 1], T g) {
+    constexpr int R = Stencil<ST>::R;
+    T sm[2 * R + 1][R + 1];
+#pragma unroll
+    for (int r = 0; r < 2 * R + 1; ++r) row_summary<T, R>(v[r], sm[r]);
+    return summary_residual<T, ST>(sm, g, v[R][R]);
+}
+
 template <typename T, int ST>
 __device__ __forceinline__ T neighbour_sum(const T (&v)[2 * Stencil<ST>::R + 1][2 * Stencil<ST>::R + 1]) {
     constexpr int R = Stencil<ST>::R;
     T sm[2 * R + 1][R + 1];
 #pragma unroll
     for (int r = 0; r < 2 * R + 1; ++r) row_summary<T, R>(v[r], sm[r]);
-    return Stencil<ST>::template combine<T>(sm);
+    return T(Stencil<ST>::scale) * Stencil<ST>::template combine<T>(sm);
 }
 
 // Hardware dispatches workgroup b to XCD b % 8.  Give every XCD a contiguous
@@ -212,7 +231,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(const T* __restrict__ uin, T
         for (int c = 0; c < W; ++c) v[W - 1][c] = p[c];
         const T gv = __builtin_nontemporal_load(g + at<T>(pitch, xl, y));
         const T uc = v[R][R];
-        const T res = (gv + neighbour_sum<T, ST>(v)) - uc;
+        const T res = window_residual<T, ST>(v, gv);
         if (NORM) acc = fmat<double>((double)res, (double)res, acc);
         if (WRITE && active) store_update<T, ST, REFL>(uout, pitch, nx, ny, x, y, fmat<T>(omega, res, uc));
     }
@@ -341,7 +360,7 @@ __device__ __forceinline__ void march_step(March<T, ST, K>& S, T (*xch)[March<T,
             }
         }
         const T uc = sm[R][0];
-        const T res = (gv + Stencil<ST>::template combine<T>(sm)) - uc;
+        const T res = summary_residual<T, ST>(sm, gv, uc);
         T un = fmat<T>(om[s - 1], res, uc);
         // boundary data: a node outside the interior keeps its value
         if (!REFL && EDGE) un = select_lane<T>(x < 1 || x > nx || Y < 1 || Y > ny, uc, un);
@@ -565,7 +584,7 @@ __global__ __launch_bounds__(256) void batch_residual_kernel(const BatchProblem*
 #pragma unroll
         for (int c = 0; c < W; ++c) v[W - 1][c] = p[c];
         const double gv = pb.g[at<double>(pitch, xl, y)];
-        const double res = (gv + neighbour_sum<double, ST>(v)) - v[R][R];
+        const double res = window_residual<double, ST>(v, gv);
         acc = fmat<double>(res, res, acc);
         if (active) {
             __builtin_nontemporal_store((float)res, pb.r32 + at<float>(pitch32, x, y));
@@ -626,7 +645,7 @@ __global__ __launch_bounds__(256) void ir_residual_kernel(const double* __restri
 #pragma unroll
         for (int c = 0; c < W; ++c) v[W - 1][c] = p[c];
         const double gv = g[at<double>(pitch, xl, y)];
-        const double res = (gv + neighbour_sum<double, ST>(v)) - v[R][R];
+        const double res = window_residual<double, ST>(v, gv);
         acc = fmat<double>(res, res, acc);
         if (active) {
             __builtin_nontemporal_store((float)res, r32 + at<float>(pitch32, x, y));
