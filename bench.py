@@ -54,7 +54,9 @@ def kernel_hash():
 def measured_traffic(n, stencil, K, rows):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary, or
     None when there is none, the kernel source changed since it was taken, or it
-    was taken for another launch geometry (K, tile rows)."""
+    holds no figure for this launch geometry (K, tile rows).  The summary gives
+    the bench's own tile height (workload line) and other heights the tile tuner
+    may pick (lines "traffic rows=R ...: bytes")."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     text = open(TRAFFIC_FILE).read()
@@ -63,9 +65,13 @@ def measured_traffic(n, stencil, K, rows):
     w = re.search(r"workload:\s*n=(\d+)\s+stencil=(\d+)\s+K=(\d+)\s+rows=(\d+)", text)
     if not (m and t and w) or m.group(1) != kernel_hash():
         return None
-    if tuple(int(v) for v in w.groups()) != (n, stencil, K, rows):
+    wn, wst, wk, wrows = (int(v) for v in w.groups())
+    if (wn, wst, wk) != (n, stencil, K):
         return None
-    return float(t.group(1))
+    if wrows == rows:
+        return float(t.group(1))
+    o = re.search(r"^traffic rows=%d\b[^:\n]*:\s*([0-9.eE+]+)" % rows, text, re.M)
+    return float(o.group(1)) if o else None
 
 
 def single_sweep_reference(cj, fd, n, st, tol, launches=48):
@@ -89,9 +95,11 @@ def single_sweep_reference(cj, fd, n, st, tol, launches=48):
             "achieved": round(achieved, 1), "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
 
 
-def traffic_probe(n, st, tol, rows=0, launches=4):
+def traffic_probe(n, st, tol, rows=(0,), launches=4):
     """Short run for rocprofv3 counter passes: a plain copy of known size (for the
-    counter calibration) and a few launches of each sweep kernel."""
+    counter calibration), a few launches of the blocked sweep in each tile height
+    of `rows` (the first is the main one; the others are told apart by their
+    workgroup counts) and a few of the single-sweep kernel."""
     import torch
     from paper_1705_00103_amd import cj, inputs
     a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")     # 1 GiB
@@ -100,14 +108,18 @@ def traffic_probe(n, st, tol, rows=0, launches=4):
         b.copy_(a)
     fd = torch.from_numpy(inputs.gaussian_bumps_rhs(n, n, seed=1705 + st)).to("cuda")
     u = torch.zeros_like(fd)
-    pk = cj.plan(n, n, st, tol, tile_rows=rows)
-    cj.sweeps(pk, fd, u, launches * pk.sweeps_per_launch)
+    geoms = []
+    for r in rows:
+        pk = cj.plan(n, n, st, tol, tile_rows=r)
+        cj.sweeps(pk, fd, u, launches * pk.sweeps_per_launch)
+        geoms.append({"rows": pk.tile_rows, "workgroups": pk.workgroups})
+    pk = cj.plan(n, n, st, tol, tile_rows=rows[0])
     p1 = cj.plan(n, n, st, tol, sweeps_per_launch=1)
     cj.sweeps(p1, fd, u, launches)
     torch.cuda.synchronize()
     print(json.dumps({"probe": "traffic", "copy_bytes_each": 2 * a.numel() * 8, "copies": 3, "n": n,
                       "stencil": st, "K": pk.sweeps_per_launch, "rows": pk.tile_rows, "blocked_launches": launches,
-                      "single_launches": launches}), flush=True)
+                      "single_launches": launches, "geometries": geoms}), flush=True)
 
 
 def cpu_baseline(f, n, stencil, tol, budget_s):
@@ -470,8 +482,9 @@ def main():
     ap.add_argument("--seed", type=int, default=None, help="RHS seed (default 1705 + stencil)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tile-rows", type=int, default=0,
-                    help="traffic probe: tile height of the blocked launches (0: the plan's default)")
+    ap.add_argument("--tile-rows", type=str, default="0",
+                    help="tile height of the blocked launches (0: the plan's default, tuned on large grids); "
+                         "traffic probe: a comma-separated list, the first being the main one")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run only the short copy + sweep probe used for rocprofv3 counter passes")
     ap.add_argument("--workload", choices=("single", "batch", "serve", "paper"), default="single",
@@ -517,7 +530,7 @@ def main():
     n, st, tol = args.n, args.stencil, args.tol
     ny = args.n if args.ny is None else args.ny
     if args.traffic_probe:
-        traffic_probe(n, st, tol, rows=args.tile_rows)
+        traffic_probe(n, st, tol, rows=[int(v) for v in args.tile_rows.split(",")])
         return
     mixed = args.precision == "f32-refine"
     seed = 1705 + st if args.seed is None else args.seed
