@@ -469,7 +469,8 @@ def run_paper(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10,
+                    help="timed steps (one solve each; p50/p99 of time-to-tol are taken over them)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=8192, help="interior nodes per axis")
     ap.add_argument("--ny", type=int, default=None, help="interior nodes in y (default: --n)")
