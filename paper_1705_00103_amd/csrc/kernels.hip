@@ -279,9 +279,9 @@ struct March {
     // level-0 rows are fetched PD row steps ahead (a row step is shorter than
     // the HBM latency under load).  Measured at 8192^2: 3-row windows gain
     // from 3 steps in FP32 and 2 in FP64 (9-point K = 8: 75.3 -> 70.1 us per
-    // sweep); 5-row windows take one step (their registers go to the wider
-    // window).
-    static constexpr int PD = (R == 2) ? 1 : sizeof(T) == 4 ? 3 : 2;
+    // sweep; 3 steps in FP64 lose: K = 10 57.0 -> 61.5); 5-row windows take
+    // two (17-point K = 4: 137.1 -> 132.3 us against one step).
+    static constexpr int PD = (R == 2) ? 2 : sizeof(T) == 4 ? 3 : 2;
     // the row loop is unrolled by U steps, a multiple of both W (window slot
     // J % W) and PD (prefetch slot J % PD), so that both rotations are static
     static constexpr int U = (W % PD == 0) ? W : W * PD;
