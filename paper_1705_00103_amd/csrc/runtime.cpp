@@ -572,7 +572,7 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol, const cj_o
     // default depths from measurements at 8192^2 on MI355X, us per sweep: FP64
     // 5- and 9-point K = 10 on grids above 2^22 points (9-point 60.4, K = 8: 62.6;
     // 5-point 56.5, K = 8: 58.7), K = 8 on smaller ones, where a cycle of whole
-    // K-launches replays as one graph; 17-point K = 4 (139.1; K = 5 no longer
+    // K-launches replays as one graph; 17-point K = 4 (132.3; K = 5 no longer
     // fits two waves per SIMD).  FP32: K = 8, 17-point K = 4.
     if (mixed) {
         // the corrections have zero boundary data in the same frame geometry
