@@ -139,6 +139,54 @@ __device__ __forceinline__ T neighbour_sum(const T (&v)[2 * Stencil<ST>::R + 1][
     return T(Stencil<ST>::scale) * Stencil<ST>::template combine<T>(sm);
 }
 
+// ------------------------------------------------------------ accurate residual
+// The refinement's outer residual r = g - D^{-1}A u decides how far the FP64
+// iterate can be corrected, so it is evaluated with error-free transformations.
+// D^{-1}A u = (W u - sum_k w_k u_k) / W with the integer weights of the stencil
+// (W = 4, 20, 300; w_k = 1; 4 and 1; 64, -4, 16 and -1).  Each w_k u_k is exact
+// (w_k is a power of two), W u is split exactly by an fma, and the terms are
+// summed with TwoSum (Knuth) carrying the compensation, so the difference of
+// magnitude ~ |g| W is formed to about a unit in its own last place instead of
+// in the last place of W |u|.  Then r = fma(-1/W, D, g).  The order of the
+// terms is fixed, so the result is deterministic.
+
+__device__ __forceinline__ void acc_two_sum(double& s, double& c, double x) {
+    const double t = s + x;
+    const double z = t - s;
+    c += (s - (t - z)) + (x - z);
+    s = t;
+}
+
+template <int ST>
+__device__ __forceinline__ double accurate_residual(const double (&v)[2 * Stencil<ST>::R + 1][2 * Stencil<ST>::R + 1],
+                                                    double g) {
+    constexpr int R = Stencil<ST>::R;
+    constexpr double W = ST == 5 ? 4.0 : ST == 9 ? 20.0 : 300.0;
+    const double u = v[R][R];
+    double s = W * u;
+    double c = __builtin_fma(W, u, -s);      // W u = s + c exactly
+#pragma unroll
+    for (int dy = -R; dy <= R; ++dy) {
+#pragma unroll
+        for (int dx = -R; dx <= R; ++dx) {
+            const int ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy;
+            double w = 0.0;
+            if (ST == 5) {
+                w = (ax + ay == 1) ? 1.0 : 0.0;
+            } else if (ST == 9) {
+                w = (ax + ay == 1) ? 4.0 : (ax == 1 && ay == 1) ? 1.0 : 0.0;
+            } else {
+                if (ax + ay == 1) w = 64.0;
+                else if ((ax == 2 && ay == 0) || (ax == 0 && ay == 2)) w = -4.0;
+                else if (ax == 1 && ay == 1) w = 16.0;
+                else if (ax == 2 && ay == 2) w = -1.0;
+            }
+            if (w != 0.0) acc_two_sum(s, c, -w * v[dy + R][dx + R]);
+        }
+    }
+    return __builtin_fma(-1.0 / W, s + c, g);
+}
+
 // Hardware dispatches workgroup b to XCD b % 8.  Give every XCD a contiguous
 // range of tiles (row-major over the grid), so that vertically adjacent tiles,
 // which share halo rows, usually run on the same XCD and share its L2.
@@ -547,7 +595,8 @@ __global__ __launch_bounds__(256) void batch_correct_kernel(const BatchProblem* 
     }
 }
 
-// Residual of one problem for its next inner solve, per tile: r32 <- (float)r,
+// Residual of one problem for its next inner solve, per tile (accurate_residual,
+// as the single-problem refinement): r32 <- (float)r,
 // the correction buffer d[dnext] <- 0 (with its reflected ring), partial sums
 // of r^2 into part[work index].
 template <int ST>
@@ -584,7 +633,7 @@ __global__ __launch_bounds__(256) void batch_residual_kernel(const BatchProblem*
 #pragma unroll
         for (int c = 0; c < W; ++c) v[W - 1][c] = p[c];
         const double gv = pb.g[at<double>(pitch, xl, y)];
-        const double res = window_residual<double, ST>(v, gv);
+        const double res = accurate_residual<ST>(v, gv);
         acc = fmat<double>(res, res, acc);
         if (active) {
             __builtin_nontemporal_store((float)res, pb.r32 + at<float>(pitch32, x, y));
@@ -609,7 +658,7 @@ __global__ __launch_bounds__(256) void segmented_reduce_kernel(const double* __r
 
 // ------------------------------------------------------------ iterative refinement
 // Residual of the FP64 iterate for the FP32 inner solve: r = g - D^{-1}A u in
-// FP64 (same expression as the sweep), rounded to FP32 into r32; the FP32
+// FP64 (accurate_residual), rounded to FP32 into r32; the FP32
 // correction d32 is reset to zero (with its reflected ring for REFL);
 // per-tile partial sums of r^2 in FP64.
 
@@ -645,7 +694,7 @@ __global__ __launch_bounds__(256) void ir_residual_kernel(const double* __restri
 #pragma unroll
         for (int c = 0; c < W; ++c) v[W - 1][c] = p[c];
         const double gv = g[at<double>(pitch, xl, y)];
-        const double res = window_residual<double, ST>(v, gv);
+        const double res = accurate_residual<ST>(v, gv);
         acc = fmat<double>(res, res, acc);
         if (active) {
             __builtin_nontemporal_store((float)res, r32 + at<float>(pitch32, x, y));
