@@ -114,10 +114,12 @@ def test_refined_solve_special_cases(torch_cuda):
     assert r["status"] == "stagnated" and r["floor_estimate"] > 0
 
 
-@pytest.mark.parametrize("n", [2047])
+@pytest.mark.parametrize("n", [2047, 4095])
 def test_refined_solve_large(torch_cuda, n):
-    """A larger grid where eps32 * kmax / kmin approaches 1e-1: the refinement still
-    meets the FP64 tolerance, checked against the exact discrete solution."""
+    """Larger grids where eps32 * kmax / kmin approaches 1e-1: the refinement still
+    meets the FP64 tolerance (at 4095^2 only with the accurately evaluated outer
+    residual; the plain sweep expression stagnates near 1.1e-10 there), checked
+    against the exact discrete solution."""
     torch = torch_cuda
     st, tol = 9, 1e-10
     f = inputs.gaussian_bumps_rhs(n, n, seed=99)
@@ -132,6 +134,6 @@ def test_refined_solve_large(torch_cuda, n):
     print("n %d: status %s, outer %d, FP32 sweeps %d, relres %.3e (oracle %.3e), err vs exact %.3e"
           % (n, r["status"], r["cycles"], r["sweeps"], r["rel_residual"], rr, err), flush=True)
     sys.stdout.flush()
-    assert r["status"] in ("ok", "stagnated")
-    assert rr <= 1e-9
+    assert r["status"] == "ok"
+    assert rr <= 2e-10      # the oracle's own FP64 evaluation adds ~7e-11 at 4095^2
     assert err <= 1e-8
