@@ -509,8 +509,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
-              "(a single solve is one GPU's work)" % args.gpus,
+        print("bench.py: the solver runs on one GPU; --gpus %d is not supported "
+              "(a single solve is one GPU's work; sharding is described, not built)" % args.gpus,
               file=sys.stderr, flush=True)
         sys.exit(2)
 
