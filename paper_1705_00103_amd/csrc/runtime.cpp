@@ -125,7 +125,7 @@ struct cj_plan_s {
         }
         return n;
     }
-    static constexpr int kTuneRows[6] = {64, 96, 128, 160, 192, 256};
+    static constexpr int kTuneRows[10] = {16, 24, 32, 48, 64, 96, 128, 160, 192, 256};
 };
 
 namespace {
@@ -351,8 +351,9 @@ cj_status tune_tile_rows(cj_plan_s* p, hipStream_t stream) {
     for (int rows : cand) {
         if (rows > ny) break;
         const cj::Tiles Tc = cj::make_tiles_k(nx, ny, K, R, rows);
-        float ms = 0.0f;
+        float ms = -1.0f;   // the faster of two launches
         for (int rep = 0; rep < 2; ++rep) {
+            float t = 0.0f;
             CJ_HIP(hipEventRecord(p->ev[0], stream));
             if (mixed)
                 CJ_HIP(cj::launch_sweepk(p->s.stencil, K, p->L32, Tc, p->D1, p->D2, p->R32, p->W32, 0, nullptr,
@@ -361,7 +362,8 @@ cj_status tune_tile_rows(cj_plan_s* p, hipStream_t stream) {
                 CJ_HIP(cj::launch_sweepk(p->s.stencil, K, p->L, Tc, p->A, p->B, p->G, p->W, 0, nullptr, stream));
             CJ_HIP(hipEventRecord(p->ev[1], stream));
             CJ_HIP(hipEventSynchronize(p->ev[1]));
-            CJ_HIP(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
+            CJ_HIP(hipEventElapsedTime(&t, p->ev[0], p->ev[1]));
+            if (ms < 0.0f || t < ms) ms = t;
         }
         if (best_ms < 0.0f || ms < best_ms) {
             best_ms = ms;
@@ -588,9 +590,11 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol, const cj_o
         if (p->K > 1) p->TK = cj::make_tiles_k(nx, ny, p->K, R, o.tile_rows);
     }
     p->D = centre_over_s(stencil) / (p->s.h * p->s.h);
-    // large grids: the tile height that fills the device best is measured
-    // (it depends on how many workgroups fit per CU and on the grid)
-    p->tune_rows = o.tile_rows == 0 && (long long)nx * ny > (1LL << 22) && (mixed ? p->K32 : p->K) > 1;
+    // grids above 2^18 points: the tile height that fills the device best is
+    // measured (it depends on how many workgroups fit per CU and on the grid;
+    // at 2048^2 the static rule's 16-row tiles spend more row steps filling the
+    // level pipeline than producing)
+    p->tune_rows = o.tile_rows == 0 && (long long)nx * ny > (1LL << 18) && (mixed ? p->K32 : p->K) > 1;
     if (o.graph < -1 || o.graph > 1) {
         delete p;
         return fail(CJ_ERR_ARG, "graph must be -1, 0 or 1");
