@@ -119,8 +119,9 @@ struct cj_plan_s {
         int n = T.count();
         if (TK.count() > n) n = TK.count();
         if (tune_rows && K > 1) {
-            // room for the flattest tile the tuner may choose
-            const int m = cj::make_tiles_k(s.nx, s.ny, K, s.stencil == 17 ? 2 : 1, kTuneRows[0]).count();
+            // room for the flattest tile the first solve may choose
+            const bool small = (long long)s.nx * s.ny <= (1LL << 18);
+            const int m = cj::make_tiles_k(s.nx, s.ny, K, s.stencil == 17 ? 2 : 1, small ? 1 : kTuneRows[0]).count();
             if (m > n) n = m;
         }
         return n;
@@ -323,17 +324,44 @@ cj_status tune_tile_rows(cj_plan_s* p, hipStream_t stream) {
     if (K <= 1) return CJ_OK;
     const int R = radius(p->s.stencil);
     const int nx = p->s.nx, ny = p->s.ny;
+    long long slots = 0;   // workgroups of the blocked kernel the device holds at once
+    int cus = 0;
+    {
+        const cj::Layout& Lk = mixed ? p->L32 : p->L;
+        int per_cu = 0;
+        const bool refl = p->s.stencil == 17 && Lk.frame == 0;
+        if (cj::sweepk_blocks_per_cu(p->s.stencil, K, Lk.elem_bytes, refl, &per_cu) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess)
+            slots = (long long)per_cu * cus;
+        (void)hipGetLastError();
+    }
+    if ((long long)nx * ny <= (1LL << 18)) {
+        // small grids: a launch costs the latency of its row pipeline, rounds x
+        // (rows + 2KR + K - 1) row steps, with the device far from full; a
+        // workgroup that shares its CU steps slower, so a round is one
+        // workgroup per CU.  Take the height that minimises that (no timing
+        // launches).
+        if (cus <= 0) return CJ_OK;
+        const long long per_round = cus;
+        const int strips = cj::make_tiles_k(nx, ny, K, R, 1).tiles_x;
+        long long best_cost = -1;
+        int best_rows = 0;
+        for (int rows = 1; rows <= 128 && rows <= ny; ++rows) {
+            const long long tiles = (long long)strips * ((ny + rows - 1) / rows);
+            const long long cost = ((tiles + per_round - 1) / per_round) * (rows + 2 * K * R + K - 1);
+            if (best_cost < 0 || cost < best_cost) {
+                best_cost = cost;
+                best_rows = rows;
+            }
+        }
+        (mixed ? p->TK32 : p->TK) = cj::make_tiles_k(nx, ny, K, R, best_rows);
+        return CJ_OK;
+    }
     // candidates: a fixed ladder, plus the heights whose tile count just fills
     // r rounds of the workgroups the device holds at once (r = 1 .. 8)
     std::vector<int> cand(std::begin(cj_plan_s::kTuneRows), std::end(cj_plan_s::kTuneRows));
     {
-        const cj::Layout& Lk = mixed ? p->L32 : p->L;
-        int per_cu = 0, cus = 0;
-        const bool refl = p->s.stencil == 17 && Lk.frame == 0;
-        if (cj::sweepk_blocks_per_cu(p->s.stencil, K, Lk.elem_bytes, refl, &per_cu) == hipSuccess &&
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess &&
-            per_cu > 0 && cus > 0) {
-            const long long slots = (long long)per_cu * cus;
+        if (slots > 0) {
             const int strips = cj::make_tiles_k(nx, ny, K, R, cj_plan_s::kTuneRows[0]).tiles_x;
             for (int r = 1; r <= 8; ++r) {
                 const long long ty = r * slots / strips;
@@ -342,7 +370,6 @@ cj_status tune_tile_rows(cj_plan_s* p, hipStream_t stream) {
                 if (rows >= cj_plan_s::kTuneRows[0] && rows <= 2048) cand.push_back((int)rows);
             }
         }
-        (void)hipGetLastError();
         std::sort(cand.begin(), cand.end());
         cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
     }
@@ -590,11 +617,12 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol, const cj_o
         if (p->K > 1) p->TK = cj::make_tiles_k(nx, ny, p->K, R, o.tile_rows);
     }
     p->D = centre_over_s(stencil) / (p->s.h * p->s.h);
-    // grids above 2^18 points: the tile height that fills the device best is
-    // measured (it depends on how many workgroups fit per CU and on the grid;
-    // at 2048^2 the static rule's 16-row tiles spend more row steps filling the
-    // level pipeline than producing)
-    p->tune_rows = o.tile_rows == 0 && (long long)nx * ny > (1LL << 18) && (mixed ? p->K32 : p->K) > 1;
+    // the tile height is chosen at the first solve, once the device is known:
+    // measured on grids above 2^18 points (it depends on how many workgroups
+    // fit per CU and on the grid; at 2048^2 the static rule's 16-row tiles spend
+    // more row steps filling the level pipeline than producing), from a cost
+    // model on smaller ones
+    p->tune_rows = o.tile_rows == 0 && (mixed ? p->K32 : p->K) > 1;
     if (o.graph < -1 || o.graph > 1) {
         delete p;
         return fail(CJ_ERR_ARG, "graph must be -1, 0 or 1");

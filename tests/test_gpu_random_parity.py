@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 
 K64 = {5: (2, 3, 4, 6, 8, 10), 9: (2, 3, 4, 6, 8, 10), 17: (2, 3, 4)}
 K32 = {5: (2, 4, 8), 9: (2, 4, 8), 17: (2, 3, 4)}
-ROWS = (0, 8, 16, 33, 64, 100)
+ROWS = (0, 1, 2, 3, 8, 16, 33, 64, 100)
 
 
 @pytest.fixture(scope="module")
