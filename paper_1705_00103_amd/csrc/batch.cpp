@@ -212,6 +212,7 @@ public:
     int Kreq = 0;
     size_t budget = 0;
     int device = -1;
+    int cus = 0;                      // compute units of the device (0: unknown)
     char* pool = nullptr;
     PoolAlloc alloc;
     std::vector<Problem*> slots;      // descriptor index -> problem (nullptr: free)
@@ -272,6 +273,10 @@ public:
         }
         device = dev;
         alloc.reset(budget);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            cus = 0;
+        }
         return CJ_OK;
     }
 
@@ -427,15 +432,34 @@ public:
                     // have at least 2048 tiles (the device is full and taller tiles
                     // waste less on their pipeline fill), shorter (down to 16) when
                     // few problems run, so that a lone small problem still spreads
-                    // over many CUs.  Tiles only partition the grid: results do not
-                    // depend on the height.
-                    int rows = 64;
-                    for (; rows > 16; rows /= 2) {
+                    // over many CUs.  Below that a launch costs the latency of its
+                    // row pipeline, rounds x (rows + 2KR + K - 1) row steps with one
+                    // workgroup per CU per round; the height from {16, 8, 4, 2, 1}
+                    // that minimises it is taken.  Tiles only partition the grid:
+                    // results do not depend on the height.
+                    auto active_tiles = [&](int r) {
                         long long tiles = 0;
                         for (Problem* p : live)
                             if (p->state == State::Active)
-                                tiles += cj::make_tiles_k(p->nx, p->ny, p->K, p->stencil == 17 ? 2 : 1, rows).count();
-                        if (tiles >= 2048) break;
+                                tiles += cj::make_tiles_k(p->nx, p->ny, p->K, p->stencil == 17 ? 2 : 1, r).count();
+                        return tiles;
+                    };
+                    int rows = 64;
+                    for (; rows > 16; rows /= 2)
+                        if (active_tiles(rows) >= 2048) break;
+                    if (rows == 16 && cus > 0 && active_tiles(16) < 2048) {
+                        int fill = 0;
+                        for (Problem* p : live)
+                            if (p->state == State::Active)
+                                fill = std::max(fill, 2 * p->K * (p->stencil == 17 ? 2 : 1) + p->K - 1);
+                        long long best = -1;
+                        for (int r = 16; r >= 1; r /= 2) {
+                            const long long cost = ((active_tiles(r) + cus - 1) / cus) * (r + fill);
+                            if (best < 0 || cost < best) {
+                                best = cost;
+                                rows = r;
+                            }
+                        }
                     }
                     for (Problem* p : live)
                         if (p->state == State::Active && p->TK.rows != std::min(rows, p->ny)) {
