@@ -108,9 +108,10 @@ typedef struct {
                                   (5/9-point) or 1, 2, 3, 4 (17-point); FP32 1, 2, 4, 8
                                   (5/9-point) or 1, 2, 3, 4 (17-point) */
     int    tile_rows;          /* rows per workgroup tile of the sweep kernel; 0 = automatic:
-                                  on grids of more than 2^22 points the first cj_solve times
-                                  the blocked kernel at several heights on the device and
-                                  keeps the fastest (results do not depend on it) */
+                                  the first cj_solve chooses it, on grids of more than 2^18
+                                  points by timing the blocked kernel at several heights on
+                                  the device, on smaller ones from a model of its row
+                                  pipeline (results do not depend on it) */
     double h;                  /* mesh spacing; 0 = 1 / max(nx + 1, ny + 1) */
     int    precision;          /* cj_precision; 0 = CJ_PRECISION_F64 */
     int    inner_M;            /* CJ_PRECISION_F32_REFINE: inner cycle length (a power of
@@ -164,10 +165,9 @@ cj_status cj_plan_info(cj_plan_t p, double* kmin, double* kmax, int* M, int* cyc
 
 /* Launch geometry of the plan's sweep kernel: sweeps fused per launch
  * (temporal-blocking depth K), output rows per workgroup tile and
- * workgroups per launch.  With tile_rows = 0 on a grid of more than 2^22
- * points the tile height is the one the first cj_solve measured fastest;
- * before that solve this reports the default.  Any output pointer may be
- * NULL. */
+ * workgroups per launch.  With tile_rows = 0 the tile height is the one the
+ * first cj_solve chose; before that solve this reports the default.  Any
+ * output pointer may be NULL. */
 cj_status cj_plan_launch_info(cj_plan_t p, int* sweeps_per_launch, int* tile_rows, int* workgroups);
 
 /* Solves A u = f.  u is read as the initial guess and overwritten with the

@@ -187,8 +187,8 @@ class Plan:
         self.refresh_launch_info()
 
     def refresh_launch_info(self):
-        """Re-reads cj_plan_launch_info (the tile height of large grids is chosen
-        on the device at the first solve)."""
+        """Re-reads cj_plan_launch_info (the tile height is chosen at the first
+        solve)."""
         k, rows, wg = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(lib().cj_plan_launch_info(self.handle, ctypes.byref(k), ctypes.byref(rows), ctypes.byref(wg)),
                "cj_plan_launch_info")
