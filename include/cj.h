@@ -184,6 +184,23 @@ cj_status cj_plan_launch_info(cj_plan_t p, int* sweeps_per_launch, int* tile_row
  * res may be NULL. */
 cj_status cj_solve(cj_plan_t p, const double* f, double* u, void* stream, cj_result* res);
 
+/* cj_solve with the iterate carried as a double-double u + u_lo: the
+ * refinement of a CJ_PRECISION_F32_REFINE plan, whose residual
+ * ||f - A (u + u_lo)|| / ||f|| is then limited by neither the rounding of the
+ * FP64 iterate nor its evaluation, so tolerances below the FP64 floor of
+ * large grids can be met.  The sweeps are the Chebyshev-weighted Jacobi
+ * iteration of §2.1 (in FP32, on the correction equation A d = r); only the
+ * outer residual and the sum u + u_lo are carried in double-double.
+ * f, u: as in cj_solve (u in: the FP64 initial guess; out: the high parts).
+ * u_lo: device array of u's shape, written only: the low parts, with
+ * |u_lo| <= ulp(u) / 2, so u alone is the solution rounded to FP64; with
+ * CJ_BC_DIRICHLET_FRAME its frame is set to zero.  u_lo must not overlap f
+ * or u.  Status and stopping rules as in cj_solve (CJ_STAGNATED: two outer
+ * steps in a row reduced the residual by less than 10%).  Uses the plan's
+ * workspace (no further device memory).  CJ_ERR_ARG for a plan of another
+ * precision or a NULL array. */
+cj_status cj_solve_dd(cj_plan_t p, const double* f, double* u, double* u_lo, void* stream, cj_result* res);
+
 /* Applies the first n_sweeps weighted sweeps of the plan's schedule (weights
  * taken cyclically) to the guess u, with no residual test; u is overwritten.
  * Same kernels and launch configuration as cj_solve.  n_sweeps >= 0.

@@ -178,6 +178,31 @@ double cjo_residual_sumsq(int nx, int ny, int stencil, double h,
     return acc;
 }
 
+/* cjo_residual_sumsq of the unevaluated sum hi + lo (a double-double
+ * iterate, both padded), in x87 extended precision (long double, 64-bit
+ * significand) throughout: the pair sum, the taps in the printed order, the
+ * division by s h^2, and the serial sum of squares. */
+double cjo_residual_sumsq_ext(int nx, int ny, int stencil, double h,
+                              const double* f, const double* hi, const double* lo)
+{
+    const struct tap* t; double s; int nt = taps_for(stencil, &t, &s);
+    if (nt == 0) return NAN;
+    const long double den = (long double)s * (long double)h * (long double)h;
+    long double acc = 0.0L;
+    for (int j = 1; j <= ny; ++j)
+        for (int i = 1; i <= nx; ++i) {
+            long double lap = 0.0L;
+            for (int k = 0; k < nt; ++k) {
+                const long double v = (long double)AT(hi, nx, i + t[k].di, j + t[k].dj)
+                                    + (long double)AT(lo, nx, i + t[k].di, j + t[k].dj);
+                lap += (long double)t[k].c * v;
+            }
+            const long double r = (long double)f[(size_t)(j - 1) * nx + (i - 1)] + lap / den;
+            acc += r * r;
+        }
+    return (double)acc;
+}
+
 /* Sum of squares of n doubles, accumulated serially in storage order. */
 double cjo_sumsq(size_t n, const double* x)
 {

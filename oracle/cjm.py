@@ -93,6 +93,8 @@ def lib():
         L.cjo_sweep.restype = c_int
         L.cjo_residual_sumsq.argtypes = [c_int, c_int, c_int, c_double, dp, dp]
         L.cjo_residual_sumsq.restype = c_double
+        L.cjo_residual_sumsq_ext.argtypes = [c_int, c_int, c_int, c_double, dp, dp, dp]
+        L.cjo_residual_sumsq_ext.restype = c_double
         L.cjo_sumsq.argtypes = [ctypes.c_size_t, dp]
         L.cjo_sumsq.restype = c_double
         L.cjo_threads.argtypes = []
@@ -357,6 +359,22 @@ def relative_residual(stencil, f, u, nx, ny, h=None, bc=BC_ZERO):
     f = np.ascontiguousarray(f, dtype=np.float64).reshape(ny, nx)
     up = _padded(u, nx, ny, stencil, bc)
     return math.sqrt(residual_sumsq(p, f, up)) / rhs_norm(p, f, up)
+
+
+def relative_residual_ext(stencil, f, u, u_lo, nx, ny, h=None, bc=BC_ZERO):
+    """relative_residual of the unevaluated sum u + u_lo (a double-double
+    iterate), the numerator evaluated in x87 extended precision (long double,
+    64-bit significand; cjo_residual_sumsq_ext): about 2^-11 of the rounding
+    of an FP64 evaluation, so it resolves residuals below the FP64 floor of
+    the grid.  The denominator is rhs_norm (FP64).  u_lo has u's shape (with
+    bc = BC_FRAME, its frame is zero)."""
+    h = spacing(nx, ny) if h is None else h
+    p = Plan(nx, ny, stencil, 1.0, M=1, h=h, bc=bc)
+    f = np.ascontiguousarray(f, dtype=np.float64).reshape(ny, nx)
+    hi = _padded(u, nx, ny, stencil, bc)
+    lo = _padded(u_lo, nx, ny, stencil, bc)
+    num = math.sqrt(lib().cjo_residual_sumsq_ext(nx, ny, stencil, h, _ptr(f), _ptr(hi), _ptr(lo)))
+    return num / rhs_norm(p, f, hi)
 
 
 def solve(f, nx, ny, stencil, tol, M=None, u0=None, max_cycles=None, h=None, method="chebyshev", bc=BC_ZERO):

@@ -42,8 +42,8 @@ STATUS_NAMES = {
 }
 
 # Function names declared in include/cj.h (checked against the header by the tests).
-EXPORTS = ("cj_options_init", "cj_plan", "cj_plan_ex", "cj_plan_info", "cj_plan_launch_info", "cj_solve", "cj_sweeps",
-           "cj_residual", "cj_apply", "cj_plan_destroy", "cj_status_string", "cj_last_error",
+EXPORTS = ("cj_options_init", "cj_plan", "cj_plan_ex", "cj_plan_info", "cj_plan_launch_info", "cj_solve",
+           "cj_solve_dd", "cj_sweeps", "cj_residual", "cj_apply", "cj_plan_destroy", "cj_status_string", "cj_last_error",
            "cj_batch_create", "cj_batch_info", "cj_batch_solve", "cj_batch_destroy",
            "cj_server_create", "cj_server_submit", "cj_server_step", "cj_server_stats", "cj_server_destroy")
 
@@ -109,6 +109,8 @@ def lib():
         L.cj_plan_launch_info.restype = c_int
         L.cj_solve.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Result)]
         L.cj_solve.restype = c_int
+        L.cj_solve_dd.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(Result)]
+        L.cj_solve_dd.restype = c_int
         L.cj_sweeps.argtypes = [vp, vp, vp, ctypes.c_longlong, vp]
         L.cj_sweeps.restype = c_int
         L.cj_residual.argtypes = [vp, vp, vp, vp, dp]
@@ -246,6 +248,18 @@ def solve(p, f, u, stream=None, raise_on_error=False):
                           ctypes.byref(r))
     if code in (CJ_ERR_ARG, CJ_ERR_NOMEM, CJ_ERR_HIP, CJ_ERR_DEVICE) or (raise_on_error and code != CJ_OK):
         raise CJError(code, "cj_solve", last_error())
+    return r.as_dict()
+
+
+def solve_dd(p, f, u, u_lo, stream=None, raise_on_error=False):
+    """cj_solve_dd: the refinement with the iterate carried as u + u_lo (a
+    CJ_PRECISION_F32_REFINE plan).  u: guess in, high parts out; u_lo (same
+    shape, must not overlap u or f): low parts out.  Result as for solve."""
+    r = Result()
+    code = lib().cj_solve_dd(p.handle, _grid_ptr(f, p, "f"), _grid_ptr(u, p, "u", True),
+                             _grid_ptr(u_lo, p, "u_lo", True), _stream(stream), ctypes.byref(r))
+    if code in (CJ_ERR_ARG, CJ_ERR_NOMEM, CJ_ERR_HIP, CJ_ERR_DEVICE) or (raise_on_error and code != CJ_OK):
+        raise CJError(code, "cj_solve_dd", last_error())
     return r.as_dict()
 
 

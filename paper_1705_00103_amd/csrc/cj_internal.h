@@ -139,11 +139,15 @@ hipError_t launch_sweepk(int stencil, int K, const Layout& L, const Tiles& T, co
 
 // Iterative refinement: r32 <- (float)(g - D^{-1}A u) and d32 <- 0 (interior
 // and reflected ring), per-tile partials of r^2 (FP64) into part.  L32 is the
-// FP32 layout of the same grid; T the single-sweep tile geometry.
+// FP32 layout of the same grid; T the single-sweep tile geometry.  With lo
+// non-null the iterate is the double-double u + lo (lo in the layout L).
 hipError_t launch_ir_residual(int stencil, const Layout& L, const Layout& L32, const Tiles& T, const double* u,
-                              const double* g, float* r32, float* d32, double* part, hipStream_t stream);
-// u += (double)d over the padded frame.
-hipError_t launch_ir_correct(const Layout& L, const Layout& L32, double* u, const float* d, hipStream_t stream);
+                              const double* lo, const double* g, float* r32, float* d32, double* part,
+                              hipStream_t stream);
+// u += (double)d over the padded frame; with lo non-null, (u, lo) += d as a
+// double-double.
+hipError_t launch_ir_correct(const Layout& L, const Layout& L32, double* u, double* lo, const float* d,
+                             hipStream_t stream);
 // Padded-frame conversions between the FP64 and FP32 layouts.
 hipError_t launch_to_f32(const Layout& L, const Layout& L32, const double* src, float* dst, hipStream_t stream);
 hipError_t launch_from_f32(const Layout& L, const Layout& L32, const float* src, double* dst, hipStream_t stream);

@@ -157,11 +157,46 @@ __device__ __forceinline__ void acc_two_sum(double& s, double& c, double x) {
     s = t;
 }
 
+// Integer weight w_k of the neighbour (dx, dy) in D^{-1}A u = (W u - sum_k w_k u_k) / W.
 template <int ST>
-__device__ __forceinline__ double accurate_residual(const double (&v)[2 * Stencil<ST>::R + 1][2 * Stencil<ST>::R + 1],
-                                                    double g) {
+__device__ __forceinline__ constexpr double stencil_weight(int dx, int dy) {
+    const int ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy;
+    if (ST == 5) return (ax + ay == 1) ? 1.0 : 0.0;
+    if (ST == 9) return (ax + ay == 1) ? 4.0 : (ax == 1 && ay == 1) ? 1.0 : 0.0;
+    if (ax + ay == 1) return 64.0;
+    if ((ax == 2 && ay == 0) || (ax == 0 && ay == 2)) return -4.0;
+    if (ax == 1 && ay == 1) return 16.0;
+    if (ax == 2 && ay == 2) return -1.0;
+    return 0.0;
+}
+
+template <int ST> constexpr double stencil_centre = ST == 5 ? 4.0 : ST == 9 ? 20.0 : 300.0;
+
+// W u - sum_k w_k u_k of a window in plain FP64, fixed order: the low part
+// of a double-double iterate, whose rounding errors are far below those of
+// the high part's exact evaluation.
+template <int ST>
+__device__ __forceinline__ double plain_scaled_operator(
+    const double (&v)[2 * Stencil<ST>::R + 1][2 * Stencil<ST>::R + 1]) {
     constexpr int R = Stencil<ST>::R;
-    constexpr double W = ST == 5 ? 4.0 : ST == 9 ? 20.0 : 300.0;
+    double t = 0.0;
+#pragma unroll
+    for (int dy = -R; dy <= R; ++dy)
+#pragma unroll
+        for (int dx = -R; dx <= R; ++dx) {
+            const double w = stencil_weight<ST>(dx, dy);
+            if (w != 0.0) t = __builtin_fma(w, v[dy + R][dx + R], t);
+        }
+    return __builtin_fma(stencil_centre<ST>, v[R][R], -t);
+}
+
+// With DD the iterate is hi + lo (v holds hi); dlo = plain_scaled_operator
+// of lo joins the compensation term before the final rounding.
+template <int ST, bool DD = false>
+__device__ __forceinline__ double accurate_residual(const double (&v)[2 * Stencil<ST>::R + 1][2 * Stencil<ST>::R + 1],
+                                                    double g, double dlo = 0.0) {
+    constexpr int R = Stencil<ST>::R;
+    constexpr double W = stencil_centre<ST>;
     const double u = v[R][R];
     double s = W * u;
     double c = __builtin_fma(W, u, -s);      // W u = s + c exactly
@@ -169,21 +204,11 @@ __device__ __forceinline__ double accurate_residual(const double (&v)[2 * Stenci
     for (int dy = -R; dy <= R; ++dy) {
 #pragma unroll
         for (int dx = -R; dx <= R; ++dx) {
-            const int ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy;
-            double w = 0.0;
-            if (ST == 5) {
-                w = (ax + ay == 1) ? 1.0 : 0.0;
-            } else if (ST == 9) {
-                w = (ax + ay == 1) ? 4.0 : (ax == 1 && ay == 1) ? 1.0 : 0.0;
-            } else {
-                if (ax + ay == 1) w = 64.0;
-                else if ((ax == 2 && ay == 0) || (ax == 0 && ay == 2)) w = -4.0;
-                else if (ax == 1 && ay == 1) w = 16.0;
-                else if (ax == 2 && ay == 2) w = -1.0;
-            }
+            const double w = stencil_weight<ST>(dx, dy);
             if (w != 0.0) acc_two_sum(s, c, -w * v[dy + R][dx + R]);
         }
     }
+    if (DD) c += dlo;
     return __builtin_fma(-1.0 / W, s + c, g);
 }
 
@@ -660,10 +685,12 @@ __global__ __launch_bounds__(256) void segmented_reduce_kernel(const double* __r
 // Residual of the FP64 iterate for the FP32 inner solve: r = g - D^{-1}A u in
 // FP64 (accurate_residual), rounded to FP32 into r32; the FP32
 // correction d32 is reset to zero (with its reflected ring for REFL);
-// per-tile partial sums of r^2 in FP64.
+// per-tile partial sums of r^2 in FP64.  With DD the iterate is the
+// double-double hi + lo (u = hi), lo in the same layout.
 
-template <int ST, bool REFL>
+template <int ST, bool REFL, bool DD>
 __global__ __launch_bounds__(256) void ir_residual_kernel(const double* __restrict__ u,
+                                                          const double* __restrict__ lo,
                                                           const double* __restrict__ g, float* __restrict__ r32,
                                                           float* __restrict__ d32, int nx, int ny, int pitch,
                                                           int pitch32, int tiles_x, int rows,
@@ -677,12 +704,16 @@ __global__ __launch_bounds__(256) void ir_residual_kernel(const double* __restri
     const int xl = active ? x : nx;
     const int y0 = ty * rows + 1;
     const int y1 = min(y0 + rows, ny + 1);
-    double v[W][W];
+    double v[W][W], vl[DD ? W : 1][W];
 #pragma unroll
     for (int r = 1; r < W; ++r) {
-        const double* p = u + at<double>(pitch, xl - R, y0 - R + r - 1);
+        const size_t o = at<double>(pitch, xl - R, y0 - R + r - 1);
 #pragma unroll
-        for (int c = 0; c < W; ++c) v[r][c] = p[c];
+        for (int c = 0; c < W; ++c) v[r][c] = u[o + c];
+        if constexpr (DD) {
+#pragma unroll
+            for (int c = 0; c < W; ++c) vl[r][c] = lo[o + c];
+        }
     }
     double acc = 0.0;
     for (int y = y0; y < y1; ++y) {
@@ -690,11 +721,21 @@ __global__ __launch_bounds__(256) void ir_residual_kernel(const double* __restri
         for (int r = 0; r < W - 1; ++r)
 #pragma unroll
             for (int c = 0; c < W; ++c) v[r][c] = v[r + 1][c];
-        const double* p = u + at<double>(pitch, xl - R, y + R);
+        const size_t o = at<double>(pitch, xl - R, y + R);
 #pragma unroll
-        for (int c = 0; c < W; ++c) v[W - 1][c] = p[c];
+        for (int c = 0; c < W; ++c) v[W - 1][c] = u[o + c];
+        double dlo = 0.0;
+        if constexpr (DD) {
+#pragma unroll
+            for (int r = 0; r < W - 1; ++r)
+#pragma unroll
+                for (int c = 0; c < W; ++c) vl[r][c] = vl[r + 1][c];
+#pragma unroll
+            for (int c = 0; c < W; ++c) vl[W - 1][c] = lo[o + c];
+            dlo = plain_scaled_operator<ST>(vl);
+        }
         const double gv = g[at<double>(pitch, xl, y)];
-        const double res = accurate_residual<ST>(v, gv);
+        const double res = accurate_residual<ST, DD>(v, gv, dlo);
         acc = fmat<double>(res, res, acc);
         if (active) {
             __builtin_nontemporal_store((float)res, r32 + at<float>(pitch32, x, y));
@@ -717,6 +758,27 @@ __global__ __launch_bounds__(256) void ir_correct_kernel(double* __restrict__ u,
     if (x > nx + 2 || y > ny + 2) return;
     double* p = u + at<double>(pitch, x, y);
     *p = *p + (double)d[at<float>(pitch32, x, y)];
+}
+
+// (hi, lo) += d over the whole padded frame, as a double-double: TwoSum of
+// hi and d, its error added to lo, and the pair renormalised by a second
+// TwoSum so that |lo| <= ulp(hi) / 2.  Round-to-nearest is symmetric, so the
+// reflected rings of hi, lo and d stay odd reflections of the interior.
+__global__ __launch_bounds__(256) void ir_correct_dd_kernel(double* __restrict__ hi, double* __restrict__ lo,
+                                                            const float* __restrict__ d, int nx, int ny, int pitch,
+                                                            int pitch32, int bx) {
+    const int x = (int)(blockIdx.x % bx) * 256 + (int)threadIdx.x - 1;
+    const int y = (int)(blockIdx.x / bx) - 1;
+    if (x > nx + 2 || y > ny + 2) return;
+    const size_t i = at<double>(pitch, x, y);
+    const double a = hi[i], b = (double)d[at<float>(pitch32, x, y)];
+    const double s = a + b;
+    const double z = s - a;
+    const double e = ((a - (s - z)) + (b - z)) + lo[i];
+    const double h = s + e;
+    const double z2 = h - s;
+    hi[i] = h;
+    lo[i] = (s - (h - z2)) + (e - z2);
 }
 
 // dst = (Tout) src over the whole padded frame.
@@ -1015,11 +1077,16 @@ hipError_t launch_residual(int stencil, const Layout& L, const Tiles& T, const d
 }
 
 hipError_t launch_ir_residual(int stencil, const Layout& L, const Layout& L32, const Tiles& T, const double* u,
-                              const double* g, float* r32, float* d32, double* part, hipStream_t stream) {
+                              const double* lo, const double* g, float* r32, float* d32, double* part,
+                              hipStream_t stream) {
     const dim3 grid(T.count()), block(T.width);
 #define CJ_IR_CASE(ST, REFL)                                                                                    \
-        hipLaunchKernelGGL((ir_residual_kernel<ST, REFL>), grid, block, 0, stream, u, g, r32, d32, L.nx, L.ny,  \
-                           L.pitch, L32.pitch, T.tiles_x, T.rows, part);
+        if (lo)                                                                                                 \
+            hipLaunchKernelGGL((ir_residual_kernel<ST, REFL, true>), grid, block, 0, stream, u, lo, g, r32,    \
+                               d32, L.nx, L.ny, L.pitch, L32.pitch, T.tiles_x, T.rows, part);                   \
+        else                                                                                                    \
+            hipLaunchKernelGGL((ir_residual_kernel<ST, REFL, false>), grid, block, 0, stream, u, lo, g, r32,   \
+                               d32, L.nx, L.ny, L.pitch, L32.pitch, T.tiles_x, T.rows, part);
     switch (stencil) {
     case 5: CJ_IR_CASE(5, false) break;
     case 9: CJ_IR_CASE(9, false) break;
@@ -1036,10 +1103,16 @@ hipError_t launch_ir_residual(int stencil, const Layout& L, const Layout& L32, c
     return hipGetLastError();
 }
 
-hipError_t launch_ir_correct(const Layout& L, const Layout& L32, double* u, const float* d, hipStream_t stream) {
+hipError_t launch_ir_correct(const Layout& L, const Layout& L32, double* u, double* lo, const float* d,
+                             hipStream_t stream) {
     int bx = 0;
     const int nb = frame_blocks(L, &bx);
-    hipLaunchKernelGGL(ir_correct_kernel, dim3(nb), dim3(256), 0, stream, u, d, L.nx, L.ny, L.pitch, L32.pitch, bx);
+    if (lo)
+        hipLaunchKernelGGL(ir_correct_dd_kernel, dim3(nb), dim3(256), 0, stream, u, lo, d, L.nx, L.ny, L.pitch,
+                           L32.pitch, bx);
+    else
+        hipLaunchKernelGGL(ir_correct_kernel, dim3(nb), dim3(256), 0, stream, u, d, L.nx, L.ny, L.pitch, L32.pitch,
+                           bx);
     return hipGetLastError();
 }
 

@@ -482,8 +482,9 @@ cj_status solve_f64(cj_plan_s* p, double gnorm, hipStream_t stream, cj_result* r
 // rounding, amplified by the growth of the partial products inside long
 // cycles, can spoil a long inner cycle while a shorter one still contracts.
 // Two consecutive outer steps that reduce the residual by less than 10% stop
-// the solve as stagnated.
-cj_status solve_refine(cj_plan_s* p, double gnorm, hipStream_t stream, cj_result* r) {
+// the solve as stagnated.  With lo non-null the iterate is the double-double
+// A + lo (lo in A's layout, zero on entry).
+cj_status solve_refine(cj_plan_s* p, double gnorm, hipStream_t stream, cj_result* r, double* lo) {
     cj_status st;
     int m = p->sin.M;
     double prev = 0.0;
@@ -491,7 +492,8 @@ cj_status solve_refine(cj_plan_s* p, double gnorm, hipStream_t stream, cj_result
     int k = 0, fails = 0;
     long long sweeps = 0;
     for (;;) {
-        CJ_HIP(cj::launch_ir_residual(p->s.stencil, p->L, p->L32, p->T, p->A, p->G, p->R32, p->D1, p->part, stream));
+        CJ_HIP(cj::launch_ir_residual(p->s.stencil, p->L, p->L32, p->T, p->A, lo, p->G, p->R32, p->D1, p->part,
+                                      stream));
         double r2 = 0.0;
         if ((st = read_sum(p, p->T.count(), stream, &r2)) != CJ_OK) return st;
         if (k > 0) {
@@ -529,12 +531,77 @@ cj_status solve_refine(cj_plan_s* p, double gnorm, hipStream_t stream, cj_result
         CJ_HIP(hipEventRecord(p->ev[1], stream));
         r->sweep_launches += launches;
         sweeps += m;
-        CJ_HIP(cj::launch_ir_correct(p->L, p->L32, p->A, cur, stream));
+        CJ_HIP(cj::launch_ir_correct(p->L, p->L32, p->A, lo, cur, stream));
         ++k;
     }
     r->cycles = k;
     r->sweeps = sweeps;
     return outcome;
+}
+
+// cj_solve, and cj_solve_dd with u_lo non-null (refinement plans only).
+cj_status solve_common(cj_plan_t p, const double* f, double* u, double* u_lo, void* stream_, cj_result* res) {
+    const auto t0 = std::chrono::steady_clock::now();
+    cj_result r{};
+    auto finish = [&](cj_status s) {
+        r.status = s;
+        r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (res) *res = r;
+        return s;
+    };
+    if (!p) return finish(fail(CJ_ERR_ARG, "plan is NULL"));
+    cj_status st;
+    if ((st = check_ptr(f, "f")) != CJ_OK || (st = check_ptr(u, "u")) != CJ_OK) return finish(st);
+    const bool dd = u_lo != nullptr;
+    const size_t u_bytes = (size_t)(p->s.nx + 2 * p->L.frame) * (size_t)(p->s.ny + 2 * p->L.frame) * sizeof(double);
+    if (dd) {
+        if (!p->mixed()) return finish(fail(CJ_ERR_ARG, "cj_solve_dd needs a CJ_PRECISION_F32_REFINE plan"));
+        if ((st = check_ptr(u_lo, "u_lo")) != CJ_OK) return finish(st);
+        const char* lo_b = reinterpret_cast<const char*>(u_lo);
+        const char* u_b = reinterpret_cast<const char*>(u);
+        const char* f_b = reinterpret_cast<const char*>(f);
+        const size_t f_bytes = (size_t)p->s.nx * (size_t)p->s.ny * sizeof(double);
+        if ((lo_b < u_b + u_bytes && u_b < lo_b + u_bytes) || (lo_b < f_b + f_bytes && f_b < lo_b + u_bytes))
+            return finish(fail(CJ_ERR_ARG, "u_lo overlaps u or f"));
+    }
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    if ((st = ensure_device(p, stream)) != CJ_OK) return finish(st);
+
+    double g2 = 0.0;
+    if ((st = stage_in(p, f, u, stream, &g2)) != CJ_OK) return finish(st);
+    if (!std::isfinite(g2)) return finish(fail(CJ_ERR_NONFINITE, "f has a NaN or Inf"));
+    if (g2 == 0.0) {
+        // zero (lifted) right-hand side: the solution is the zero interior,
+        // which B holds with a frame
+        hipError_t e = p->L.frame > 0
+                           ? cj::launch_stage_out(p->L, p->B, u, stream)
+                           : hipMemsetAsync(u, 0, (size_t)p->s.nx * (size_t)p->s.ny * sizeof(double), stream);
+        if (e == hipSuccess && dd) e = hipMemsetAsync(u_lo, 0, u_bytes, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return finish(fail(CJ_ERR_HIP, hipGetErrorString(e)));
+        return finish(CJ_OK);
+    }
+    const double gnorm = std::sqrt(g2);
+    double* answer = p->A;
+    cj_status outcome;
+    if ((st = tune_tile_rows(p, stream)) != CJ_OK) return finish(st);
+    // the refinement does not use the second iterate B: it holds the low
+    // parts of a double-double iterate, zero over the whole padded frame
+    if (dd) {
+        const hipError_t e = hipMemsetAsync(p->B, 0, p->L.elems * sizeof(double), stream);
+        if (e != hipSuccess) return finish(fail(CJ_ERR_HIP, hipGetErrorString(e)));
+    }
+    if (p->mixed())
+        outcome = solve_refine(p, gnorm, stream, &r, dd ? p->B : nullptr);
+    else
+        outcome = solve_f64(p, gnorm, stream, &r, &answer);
+    if (outcome == CJ_ERR_HIP) return finish(outcome);
+    hipError_t e = cj::launch_stage_out(p->L, answer, u, stream);
+    if (e == hipSuccess && dd) e = hipMemsetAsync(u_lo, 0, u_bytes, stream);
+    if (e == hipSuccess && dd) e = cj::launch_stage_out(p->L, p->B, u_lo, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return finish(fail(CJ_ERR_HIP, hipGetErrorString(e)));
+    return finish(outcome);
 }
 
 }  // namespace
@@ -664,47 +731,19 @@ cj_status cj_plan_launch_info(cj_plan_t p, int* sweeps_per_launch, int* tile_row
     return CJ_OK;
 }
 
-cj_status cj_solve(cj_plan_t p, const double* f, double* u, void* stream_, cj_result* res) {
-    const auto t0 = std::chrono::steady_clock::now();
-    cj_result r{};
-    auto finish = [&](cj_status s) {
+cj_status cj_solve(cj_plan_t p, const double* f, double* u, void* stream, cj_result* res) {
+    return solve_common(p, f, u, nullptr, stream, res);
+}
+
+cj_status cj_solve_dd(cj_plan_t p, const double* f, double* u, double* u_lo, void* stream, cj_result* res) {
+    if (!u_lo) {
+        cj_result r{};
+        const cj_status s = fail(CJ_ERR_ARG, "u_lo is NULL");
         r.status = s;
-        r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (res) *res = r;
         return s;
-    };
-    if (!p) return finish(fail(CJ_ERR_ARG, "plan is NULL"));
-    cj_status st;
-    if ((st = check_ptr(f, "f")) != CJ_OK || (st = check_ptr(u, "u")) != CJ_OK) return finish(st);
-    hipStream_t stream = static_cast<hipStream_t>(stream_);
-    if ((st = ensure_device(p, stream)) != CJ_OK) return finish(st);
-
-    double g2 = 0.0;
-    if ((st = stage_in(p, f, u, stream, &g2)) != CJ_OK) return finish(st);
-    if (!std::isfinite(g2)) return finish(fail(CJ_ERR_NONFINITE, "f has a NaN or Inf"));
-    if (g2 == 0.0) {
-        // zero (lifted) right-hand side: the solution is the zero interior,
-        // which B holds with a frame
-        hipError_t e = p->L.frame > 0
-                           ? cj::launch_stage_out(p->L, p->B, u, stream)
-                           : hipMemsetAsync(u, 0, (size_t)p->s.nx * (size_t)p->s.ny * sizeof(double), stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(stream);
-        if (e != hipSuccess) return finish(fail(CJ_ERR_HIP, hipGetErrorString(e)));
-        return finish(CJ_OK);
     }
-    const double gnorm = std::sqrt(g2);
-    double* answer = p->A;
-    cj_status outcome;
-    if ((st = tune_tile_rows(p, stream)) != CJ_OK) return finish(st);
-    if (p->mixed())
-        outcome = solve_refine(p, gnorm, stream, &r);
-    else
-        outcome = solve_f64(p, gnorm, stream, &r, &answer);
-    if (outcome == CJ_ERR_HIP) return finish(outcome);
-    hipError_t e = cj::launch_stage_out(p->L, answer, u, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return finish(fail(CJ_ERR_HIP, hipGetErrorString(e)));
-    return finish(outcome);
+    return solve_common(p, f, u, u_lo, stream, res);
 }
 
 cj_status cj_sweeps(cj_plan_t p, const double* f, double* u, long long n_sweeps, void* stream_) {

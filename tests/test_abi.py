@@ -96,6 +96,8 @@ def test_null_arguments_are_errors_not_crashes():
     assert L.cj_sweeps(p.handle, ctypes.c_void_p(4096), ctypes.c_void_p(4096), -1, None) == cj.CJ_ERR_ARG
     assert L.cj_residual(p.handle, ctypes.c_void_p(4096), ctypes.c_void_p(4096), None, None) == cj.CJ_ERR_ARG
     assert L.cj_apply(p.handle, None, None, None) == cj.CJ_ERR_ARG
+    assert L.cj_solve_dd(None, None, None, None, None, None) == cj.CJ_ERR_ARG
+    assert L.cj_solve_dd(p.handle, ctypes.c_void_p(4096), ctypes.c_void_p(8192), None, None, None) == cj.CJ_ERR_ARG
     L.cj_plan_destroy(None)
     p.destroy()
     p.destroy()
