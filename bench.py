@@ -474,9 +474,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=8192, help="interior nodes per axis")
     ap.add_argument("--ny", type=int, default=None, help="interior nodes in y (default: --n)")
-    ap.add_argument("--precision", choices=("f64", "f32-refine", "f32-refine-dd"), default="f64",
+    ap.add_argument("--precision", choices=("f64", "f32-refine", "f32-refine-dd", "f64-dd"), default="f64",
                     help="f64: the plain FP64 solve; f32-refine: FP32 sweeps inside FP64 refinement; "
-                         "f32-refine-dd: the same with the iterate carried as a double-double (cj_solve_dd)")
+                         "f32-refine-dd: the same with the iterate carried as a double-double (cj_solve_dd); "
+                         "f64-dd: cj_solve_dd of an FP64 plan (one FP64 cycle per outer step)")
     ap.add_argument("--reference-f64", action="store_true",
                     help="with --precision f32-refine: also run one plain FP64 solve and report the difference")
     ap.add_argument("--stencil", type=int, default=9, choices=(5, 9, 17))
@@ -535,7 +536,7 @@ def main():
         traffic_probe(n, st, tol, rows=[int(v) for v in args.tile_rows.split(",")])
         return
     mixed = args.precision in ("f32-refine", "f32-refine-dd")
-    dd = args.precision == "f32-refine-dd"
+    dd = args.precision in ("f32-refine-dd", "f64-dd")
     seed = 1705 + st if args.seed is None else args.seed
     f = inputs.gaussian_bumps_rhs(n, ny, seed=seed)
     fd = torch.from_numpy(f).to("cuda")
@@ -617,11 +618,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ("f32+f64x2" if dd else "f32+f64") if mixed else "f64",
+        "dtype": ("f32+f64x2" if dd else "f32+f64") if mixed else ("f64x2" if dd else "f64"),
         "data": "synthetic",
         "config": {
             "workload": "cjm-%s-%dpt-%dx%d-bumps16-tol%g" % (
-                ("f32refine-dd" if dd else "f32refine") if mixed else "fp64", st, n, ny, tol),
+                ("f32refine-dd" if dd else "f32refine") if mixed else ("fp64-dd" if dd else "fp64"), st, n, ny, tol),
             "nx": n, "ny": ny, "stencil": st, "tol": tol, "rhs_seed": seed, "M": p.M,
             "cycles_pred": p.cycles_pred, "sweeps_per_launch": K, "tile_rows": p.tile_rows,
             "parallelism": "single-gpu",

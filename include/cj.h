@@ -184,21 +184,25 @@ cj_status cj_plan_launch_info(cj_plan_t p, int* sweeps_per_launch, int* tile_row
  * res may be NULL. */
 cj_status cj_solve(cj_plan_t p, const double* f, double* u, void* stream, cj_result* res);
 
-/* cj_solve with the iterate carried as a double-double u + u_lo: the
- * refinement of a CJ_PRECISION_F32_REFINE plan, whose residual
- * ||f - A (u + u_lo)|| / ||f|| is then limited by neither the rounding of the
- * FP64 iterate nor its evaluation, so tolerances below the FP64 floor of
- * large grids can be met.  The sweeps are the Chebyshev-weighted Jacobi
- * iteration of §2.1 (in FP32, on the correction equation A d = r); only the
- * outer residual and the sum u + u_lo are carried in double-double.
+/* cj_solve with the iterate carried as a double-double u + u_lo: iterative
+ * refinement whose residual ||f - A (u + u_lo)|| / ||f|| is limited by
+ * neither the rounding of an FP64 iterate nor its evaluation, so tolerances
+ * below the FP64 floor of large grids can be met.  Each outer step evaluates
+ * the residual of u + u_lo (error-free transformations), solves the
+ * correction equation A d = r approximately and adds d into the pair.  The
+ * correction is the Chebyshev-weighted Jacobi iteration of §2.1:
+ *   CJ_PRECISION_F32_REFINE plans: one inner FP32 cycle, as in cj_solve;
+ *   CJ_PRECISION_F64 plans: one FP64 cycle of the plan's own schedule (no
+ *     limit from FP32 rounding on the largest grids; the first call
+ *     allocates three more padded FP64 arrays, kept by the plan).
  * f, u: as in cj_solve (u in: the FP64 initial guess; out: the high parts).
  * u_lo: device array of u's shape, written only: the low parts, with
  * |u_lo| <= ulp(u) / 2, so u alone is the solution rounded to FP64; with
  * CJ_BC_DIRICHLET_FRAME its frame is set to zero.  u_lo must not overlap f
- * or u.  Status and stopping rules as in cj_solve (CJ_STAGNATED: two outer
- * steps in a row reduced the residual by less than 10%).  Uses the plan's
- * workspace (no further device memory).  CJ_ERR_ARG for a plan of another
- * precision or a NULL array. */
+ * or u.  Status as in cj_solve; CJ_STAGNATED: two outer steps in a row
+ * reduced the residual by less than 10%; CJ_ERR_NOT_CONVERGED after
+ * max_cycles outer steps.  CJ_ERR_ARG for a CJ_METHOD_JACOBI plan or a NULL
+ * array. */
 cj_status cj_solve_dd(cj_plan_t p, const double* f, double* u, double* u_lo, void* stream, cj_result* res);
 
 /* Applies the first n_sweeps weighted sweeps of the plan's schedule (weights

@@ -252,9 +252,10 @@ def solve(p, f, u, stream=None, raise_on_error=False):
 
 
 def solve_dd(p, f, u, u_lo, stream=None, raise_on_error=False):
-    """cj_solve_dd: the refinement with the iterate carried as u + u_lo (a
-    CJ_PRECISION_F32_REFINE plan).  u: guess in, high parts out; u_lo (same
-    shape, must not overlap u or f): low parts out.  Result as for solve."""
+    """cj_solve_dd: iterative refinement with the iterate carried as u + u_lo
+    (inner FP32 cycles for an F32_REFINE plan, FP64 cycles for an F64 plan).
+    u: guess in, high parts out; u_lo (same shape, must not overlap u or f):
+    low parts out.  Result as for solve."""
     r = Result()
     code = lib().cj_solve_dd(p.handle, _grid_ptr(f, p, "f"), _grid_ptr(u, p, "u", True),
                              _grid_ptr(u_lo, p, "u_lo", True), _stream(stream), ctypes.byref(r))

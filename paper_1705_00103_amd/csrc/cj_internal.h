@@ -144,10 +144,15 @@ hipError_t launch_sweepk(int stencil, int K, const Layout& L, const Tiles& T, co
 hipError_t launch_ir_residual(int stencil, const Layout& L, const Layout& L32, const Tiles& T, const double* u,
                               const double* lo, const double* g, float* r32, float* d32, double* part,
                               hipStream_t stream);
+// The same with an FP64 inner solve: r and d in the FP64 layout L.
+hipError_t launch_ir_residual(int stencil, const Layout& L, const Tiles& T, const double* u, const double* lo,
+                              const double* g, double* r, double* d, double* part, hipStream_t stream);
 // u += (double)d over the padded frame; with lo non-null, (u, lo) += d as a
 // double-double.
 hipError_t launch_ir_correct(const Layout& L, const Layout& L32, double* u, double* lo, const float* d,
                              hipStream_t stream);
+// (u, lo) += d (FP64, layout L) as a double-double; lo must be non-null.
+hipError_t launch_ir_correct(const Layout& L, double* u, double* lo, const double* d, hipStream_t stream);
 // Padded-frame conversions between the FP64 and FP32 layouts.
 hipError_t launch_to_f32(const Layout& L, const Layout& L32, const double* src, float* dst, hipStream_t stream);
 hipError_t launch_from_f32(const Layout& L, const Layout& L32, const float* src, double* dst, hipStream_t stream);

@@ -682,17 +682,18 @@ __global__ __launch_bounds__(256) void segmented_reduce_kernel(const double* __r
 }
 
 // ------------------------------------------------------------ iterative refinement
-// Residual of the FP64 iterate for the FP32 inner solve: r = g - D^{-1}A u in
-// FP64 (accurate_residual), rounded to FP32 into r32; the FP32
-// correction d32 is reset to zero (with its reflected ring for REFL);
-// per-tile partial sums of r^2 in FP64.  With DD the iterate is the
-// double-double hi + lo (u = hi), lo in the same layout.
+// Residual of the FP64 iterate for the inner solve: r = g - D^{-1}A u in
+// FP64 (accurate_residual), stored in the inner precision TR (rounded to
+// FP32, or kept in FP64) into r32; the correction d32 (also TR) is reset to
+// zero (with its reflected ring for REFL); per-tile partial sums of r^2 in
+// FP64.  With DD the iterate is the double-double hi + lo (u = hi), lo in
+// the same layout.
 
-template <int ST, bool REFL, bool DD>
+template <int ST, bool REFL, bool DD, typename TR>
 __global__ __launch_bounds__(256) void ir_residual_kernel(const double* __restrict__ u,
                                                           const double* __restrict__ lo,
-                                                          const double* __restrict__ g, float* __restrict__ r32,
-                                                          float* __restrict__ d32, int nx, int ny, int pitch,
+                                                          const double* __restrict__ g, TR* __restrict__ r32,
+                                                          TR* __restrict__ d32, int nx, int ny, int pitch,
                                                           int pitch32, int tiles_x, int rows,
                                                           double* __restrict__ part) {
     constexpr int R = Stencil<ST>::R;
@@ -738,8 +739,8 @@ __global__ __launch_bounds__(256) void ir_residual_kernel(const double* __restri
         const double res = accurate_residual<ST, DD>(v, gv, dlo);
         acc = fmat<double>(res, res, acc);
         if (active) {
-            __builtin_nontemporal_store((float)res, r32 + at<float>(pitch32, x, y));
-            store_update<float, ST, REFL>(d32, pitch32, nx, ny, x, y, 0.0f);
+            __builtin_nontemporal_store((TR)res, r32 + at<TR>(pitch32, x, y));
+            store_update<TR, ST, REFL>(d32, pitch32, nx, ny, x, y, TR(0));
         }
     }
     if (!active) acc = 0.0;
@@ -764,14 +765,15 @@ __global__ __launch_bounds__(256) void ir_correct_kernel(double* __restrict__ u,
 // hi and d, its error added to lo, and the pair renormalised by a second
 // TwoSum so that |lo| <= ulp(hi) / 2.  Round-to-nearest is symmetric, so the
 // reflected rings of hi, lo and d stay odd reflections of the interior.
+template <typename TD>
 __global__ __launch_bounds__(256) void ir_correct_dd_kernel(double* __restrict__ hi, double* __restrict__ lo,
-                                                            const float* __restrict__ d, int nx, int ny, int pitch,
+                                                            const TD* __restrict__ d, int nx, int ny, int pitch,
                                                             int pitch32, int bx) {
     const int x = (int)(blockIdx.x % bx) * 256 + (int)threadIdx.x - 1;
     const int y = (int)(blockIdx.x / bx) - 1;
     if (x > nx + 2 || y > ny + 2) return;
     const size_t i = at<double>(pitch, x, y);
-    const double a = hi[i], b = (double)d[at<float>(pitch32, x, y)];
+    const double a = hi[i], b = (double)d[at<TD>(pitch32, x, y)];
     const double s = a + b;
     const double z = s - a;
     const double e = ((a - (s - z)) + (b - z)) + lo[i];
@@ -1076,17 +1078,19 @@ hipError_t launch_residual(int stencil, const Layout& L, const Tiles& T, const d
     }
 }
 
-hipError_t launch_ir_residual(int stencil, const Layout& L, const Layout& L32, const Tiles& T, const double* u,
-                              const double* lo, const double* g, float* r32, float* d32, double* part,
-                              hipStream_t stream) {
+namespace {
+
+template <typename TR>
+hipError_t ir_residual_launch(int stencil, const Layout& L, const Layout& LR, const Tiles& T, const double* u,
+                              const double* lo, const double* g, TR* r, TR* d, double* part, hipStream_t stream) {
     const dim3 grid(T.count()), block(T.width);
 #define CJ_IR_CASE(ST, REFL)                                                                                    \
         if (lo)                                                                                                 \
-            hipLaunchKernelGGL((ir_residual_kernel<ST, REFL, true>), grid, block, 0, stream, u, lo, g, r32,    \
-                               d32, L.nx, L.ny, L.pitch, L32.pitch, T.tiles_x, T.rows, part);                   \
+            hipLaunchKernelGGL((ir_residual_kernel<ST, REFL, true, TR>), grid, block, 0, stream, u, lo, g, r,  \
+                               d, L.nx, L.ny, L.pitch, LR.pitch, T.tiles_x, T.rows, part);                      \
         else                                                                                                    \
-            hipLaunchKernelGGL((ir_residual_kernel<ST, REFL, false>), grid, block, 0, stream, u, lo, g, r32,   \
-                               d32, L.nx, L.ny, L.pitch, L32.pitch, T.tiles_x, T.rows, part);
+            hipLaunchKernelGGL((ir_residual_kernel<ST, REFL, false, TR>), grid, block, 0, stream, u, lo, g, r, \
+                               d, L.nx, L.ny, L.pitch, LR.pitch, T.tiles_x, T.rows, part);
     switch (stencil) {
     case 5: CJ_IR_CASE(5, false) break;
     case 9: CJ_IR_CASE(9, false) break;
@@ -1103,17 +1107,42 @@ hipError_t launch_ir_residual(int stencil, const Layout& L, const Layout& L32, c
     return hipGetLastError();
 }
 
-hipError_t launch_ir_correct(const Layout& L, const Layout& L32, double* u, double* lo, const float* d,
+template <typename TD>
+hipError_t ir_correct_launch(const Layout& L, const Layout& LD, double* u, double* lo, const TD* d,
                              hipStream_t stream) {
     int bx = 0;
     const int nb = frame_blocks(L, &bx);
     if (lo)
-        hipLaunchKernelGGL(ir_correct_dd_kernel, dim3(nb), dim3(256), 0, stream, u, lo, d, L.nx, L.ny, L.pitch,
-                           L32.pitch, bx);
-    else
-        hipLaunchKernelGGL(ir_correct_kernel, dim3(nb), dim3(256), 0, stream, u, d, L.nx, L.ny, L.pitch, L32.pitch,
+        hipLaunchKernelGGL((ir_correct_dd_kernel<TD>), dim3(nb), dim3(256), 0, stream, u, lo, d, L.nx, L.ny,
+                           L.pitch, LD.pitch, bx);
+    else if constexpr (sizeof(TD) == 4)
+        hipLaunchKernelGGL(ir_correct_kernel, dim3(nb), dim3(256), 0, stream, u, d, L.nx, L.ny, L.pitch, LD.pitch,
                            bx);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_ir_residual(int stencil, const Layout& L, const Layout& L32, const Tiles& T, const double* u,
+                              const double* lo, const double* g, float* r32, float* d32, double* part,
+                              hipStream_t stream) {
+    return ir_residual_launch<float>(stencil, L, L32, T, u, lo, g, r32, d32, part, stream);
+}
+
+hipError_t launch_ir_residual(int stencil, const Layout& L, const Tiles& T, const double* u, const double* lo,
+                              const double* g, double* r, double* d, double* part, hipStream_t stream) {
+    return ir_residual_launch<double>(stencil, L, L, T, u, lo, g, r, d, part, stream);
+}
+
+hipError_t launch_ir_correct(const Layout& L, const Layout& L32, double* u, double* lo, const float* d,
+                             hipStream_t stream) {
+    return ir_correct_launch<float>(L, L32, u, lo, d, stream);
+}
+
+hipError_t launch_ir_correct(const Layout& L, double* u, double* lo, const double* d, hipStream_t stream) {
+    return ir_correct_launch<double>(L, L, u, lo, d, stream);
 }
 
 hipError_t launch_to_f32(const Layout& L, const Layout& L32, const double* src, float* dst, hipStream_t stream) {

@@ -96,6 +96,11 @@ struct cj_plan_s {
     float* D1 = nullptr;
     float* D2 = nullptr;
     float* W32 = nullptr;
+    // double-double solves of FP64 plans (allocated by the first one): the
+    // FP64 inner right-hand side and the two iterates of the correction
+    double* R64 = nullptr;
+    double* E1 = nullptr;
+    double* E2 = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};   // bracket the plain sweeps of a cycle
     // The plain launches of an FP64 cycle (all but the first, norm-fused one),
     // captured once as a graph on a private stream and replayed every cycle.
@@ -137,7 +142,8 @@ void release(cj_plan_s* p) {
         (void)hipGetDevice(&cur);
         (void)hipSetDevice(p->device);
         for (void* d : {(void*)p->A, (void*)p->B, (void*)p->G, (void*)p->W, (void*)p->part, (void*)p->scalar,
-                        (void*)p->R32, (void*)p->D1, (void*)p->D2, (void*)p->W32})
+                        (void*)p->R32, (void*)p->D1, (void*)p->D2, (void*)p->W32, (void*)p->R64, (void*)p->E1,
+                        (void*)p->E2})
             if (d) (void)hipFree(d);
         if (p->host_slot) (void)hipHostFree(p->host_slot);
         for (hipEvent_t& e : p->ev)
@@ -149,6 +155,7 @@ void release(cj_plan_s* p) {
     }
     p->A = p->B = p->G = p->W = p->part = p->scalar = p->host_slot = nullptr;
     p->R32 = p->D1 = p->D2 = p->W32 = nullptr;
+    p->R64 = p->E1 = p->E2 = nullptr;
     p->ev[0] = p->ev[1] = nullptr;
     p->graph_exec = nullptr;
     p->graph = nullptr;
@@ -483,8 +490,11 @@ cj_status solve_f64(cj_plan_s* p, double gnorm, hipStream_t stream, cj_result* r
 // cycles, can spoil a long inner cycle while a shorter one still contracts.
 // Two consecutive outer steps that reduce the residual by less than 10% stop
 // the solve as stagnated.  With lo non-null the iterate is the double-double
-// A + lo (lo in A's layout, zero on entry).
+// A + lo (lo in A's layout, zero on entry).  An FP64 plan (double-double
+// only) corrects with one FP64 cycle of its own schedule per outer step
+// instead, on the buffers R64, E1 and E2.
 cj_status solve_refine(cj_plan_s* p, double gnorm, hipStream_t stream, cj_result* r, double* lo) {
+    const bool f64 = !p->mixed();
     cj_status st;
     int m = p->sin.M;
     double prev = 0.0;
@@ -492,8 +502,11 @@ cj_status solve_refine(cj_plan_s* p, double gnorm, hipStream_t stream, cj_result
     int k = 0, fails = 0;
     long long sweeps = 0;
     for (;;) {
-        CJ_HIP(cj::launch_ir_residual(p->s.stencil, p->L, p->L32, p->T, p->A, lo, p->G, p->R32, p->D1, p->part,
-                                      stream));
+        if (f64)
+            CJ_HIP(cj::launch_ir_residual(p->s.stencil, p->L, p->T, p->A, lo, p->G, p->R64, p->E1, p->part, stream));
+        else
+            CJ_HIP(cj::launch_ir_residual(p->s.stencil, p->L, p->L32, p->T, p->A, lo, p->G, p->R32, p->D1, p->part,
+                                          stream));
         double r2 = 0.0;
         if ((st = read_sum(p, p->T.count(), stream, &r2)) != CJ_OK) return st;
         if (k > 0) {
@@ -521,17 +534,29 @@ cj_status solve_refine(cj_plan_s* p, double gnorm, hipStream_t stream, cj_result
             stop = false;
         }
         if (stop) break;
-        if (k >= 1 && q > 0.5 && m > 16) m /= 2;
         prev = rr;
-        float* cur = p->D1;
-        float* nxt = p->D2;
         long long launches = 0;
-        CJ_HIP(hipEventRecord(p->ev[0], stream));
-        if ((st = enqueue_f32(p, m, 0, m, &cur, &nxt, stream, &launches)) != CJ_OK) return st;
-        CJ_HIP(hipEventRecord(p->ev[1], stream));
+        if (f64) {
+            double* cur = p->E1;
+            double* nxt = p->E2;
+            CJ_HIP(hipEventRecord(p->ev[0], stream));
+            if ((st = enqueue_sweeps<double>(p, p->s.M, p->K, p->L, p->TK, p->R64, p->W, 0, p->s.M, &cur, &nxt,
+                                             stream, nullptr, &launches)) != CJ_OK)
+                return st;
+            CJ_HIP(hipEventRecord(p->ev[1], stream));
+            sweeps += p->s.M;
+            CJ_HIP(cj::launch_ir_correct(p->L, p->A, lo, cur, stream));
+        } else {
+            if (k >= 1 && q > 0.5 && m > 16) m /= 2;
+            float* cur = p->D1;
+            float* nxt = p->D2;
+            CJ_HIP(hipEventRecord(p->ev[0], stream));
+            if ((st = enqueue_f32(p, m, 0, m, &cur, &nxt, stream, &launches)) != CJ_OK) return st;
+            CJ_HIP(hipEventRecord(p->ev[1], stream));
+            sweeps += m;
+            CJ_HIP(cj::launch_ir_correct(p->L, p->L32, p->A, lo, cur, stream));
+        }
         r->sweep_launches += launches;
-        sweeps += m;
-        CJ_HIP(cj::launch_ir_correct(p->L, p->L32, p->A, lo, cur, stream));
         ++k;
     }
     r->cycles = k;
@@ -555,7 +580,8 @@ cj_status solve_common(cj_plan_t p, const double* f, double* u, double* u_lo, vo
     const bool dd = u_lo != nullptr;
     const size_t u_bytes = (size_t)(p->s.nx + 2 * p->L.frame) * (size_t)(p->s.ny + 2 * p->L.frame) * sizeof(double);
     if (dd) {
-        if (!p->mixed()) return finish(fail(CJ_ERR_ARG, "cj_solve_dd needs a CJ_PRECISION_F32_REFINE plan"));
+        if (p->opt.method != CJ_METHOD_CHEBYSHEV)
+            return finish(fail(CJ_ERR_ARG, "cj_solve_dd needs a Chebyshev-Jacobi plan"));
         if ((st = check_ptr(u_lo, "u_lo")) != CJ_OK) return finish(st);
         const char* lo_b = reinterpret_cast<const char*>(u_lo);
         const char* u_b = reinterpret_cast<const char*>(u);
@@ -566,6 +592,25 @@ cj_status solve_common(cj_plan_t p, const double* f, double* u, double* u_lo, vo
     }
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     if ((st = ensure_device(p, stream)) != CJ_OK) return finish(st);
+    if (dd && !p->mixed() && !p->R64) {
+        const size_t bytes = p->L.elems * sizeof(double);
+        hipError_t e = hipMalloc((void**)&p->R64, bytes);
+        if (e == hipSuccess) e = hipMalloc((void**)&p->E1, bytes);
+        if (e == hipSuccess) e = hipMalloc((void**)&p->E2, bytes);
+        // the corrections' Dirichlet rings stay zero for the life of the plan
+        if (e == hipSuccess) e = hipMemsetAsync(p->R64, 0, bytes, stream);
+        if (e == hipSuccess) e = hipMemsetAsync(p->E1, 0, bytes, stream);
+        if (e == hipSuccess) e = hipMemsetAsync(p->E2, 0, bytes, stream);
+        if (e != hipSuccess) {
+            for (double** b : {&p->R64, &p->E1, &p->E2}) {
+                if (*b) (void)hipFree(*b);
+                *b = nullptr;
+            }
+            (void)hipGetLastError();
+            return finish(fail(e == hipErrorOutOfMemory ? CJ_ERR_NOMEM : CJ_ERR_HIP,
+                               std::string("double-double workspace: ") + hipGetErrorString(e)));
+        }
+    }
 
     double g2 = 0.0;
     if ((st = stage_in(p, f, u, stream, &g2)) != CJ_OK) return finish(st);
@@ -591,7 +636,7 @@ cj_status solve_common(cj_plan_t p, const double* f, double* u, double* u_lo, vo
         const hipError_t e = hipMemsetAsync(p->B, 0, p->L.elems * sizeof(double), stream);
         if (e != hipSuccess) return finish(fail(CJ_ERR_HIP, hipGetErrorString(e)));
     }
-    if (p->mixed())
+    if (p->mixed() || dd)
         outcome = solve_refine(p, gnorm, stream, &r, dd ? p->B : nullptr);
     else
         outcome = solve_f64(p, gnorm, stream, &r, &answer);

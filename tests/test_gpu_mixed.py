@@ -139,13 +139,18 @@ def test_refined_solve_large(torch_cuda, n):
     assert err <= 1e-8
 
 
+DD_PRECISIONS = [pytest.param(cj.F32_REFINE, id="f32inner"), pytest.param(cj.F64, id="f64inner")]
+
+
+@pytest.mark.parametrize("precision", DD_PRECISIONS)
 @pytest.mark.parametrize("st", [5, 9, 17])
 @pytest.mark.parametrize("frame", [False, True])
-def test_double_double_solve_below_the_fp64_floor(torch_cuda, st, frame):
+def test_double_double_solve_below_the_fp64_floor(torch_cuda, st, frame, precision):
     """cj_solve_dd carries the iterate as u + u_lo: it meets a tolerance far
     below what an FP64 iterate can reach, judged by the oracle's residual of
     u + u_lo in extended precision; u_lo is the low part (|u_lo| <= ulp(u)/2),
-    the frame comes back as given and u_lo's frame is zero."""
+    the frame comes back as given and u_lo's frame is zero.  Inner FP32 cycles
+    (refinement plans) and FP64 cycles (FP64 plans)."""
     torch = torch_cuda
     nx, ny, tol = 301, 233, 3e-15
     f = inputs.gaussian_bumps_rhs(nx, ny, seed=40 + st)
@@ -155,7 +160,7 @@ def test_double_double_solve_below_the_fp64_floor(torch_cuda, st, frame):
         u0 = inputs.expxy_frame(nx, ny, G)
     else:
         u0 = np.zeros((ny, nx))
-    p = cj.plan(nx, ny, st, tol, precision=cj.F32_REFINE, bc=bc, max_cycles=60)
+    p = cj.plan(nx, ny, st, tol, precision=precision, bc=bc, max_cycles=60)
     u = _dev(torch, u0)
     lo = torch.full_like(u, 7.0)       # written only
     r = cj.solve_dd(p, _dev(torch, f), u, lo)
@@ -163,8 +168,8 @@ def test_double_double_solve_below_the_fp64_floor(torch_cuda, st, frame):
     obc = cjm.BC_FRAME if frame else cjm.BC_ZERO
     ext = cjm.relative_residual_ext(st, f, hi, lo, nx, ny, bc=obc)
     ext_hi = cjm.relative_residual_ext(st, f, hi, np.zeros_like(lo), nx, ny, bc=obc)
-    print("st %d frame %d: status %s, outer %d, relres %.3e, oracle (extended) %.3e, of u alone %.3e"
-          % (st, frame, r["status"], r["cycles"], r["rel_residual"], ext, ext_hi), flush=True)
+    print("st %d frame %d precision %d: status %s, outer %d, relres %.3e, oracle (extended) %.3e, of u alone %.3e"
+          % (st, frame, precision, r["status"], r["cycles"], r["rel_residual"], ext, ext_hi), flush=True)
     assert r["status"] == "ok" and r["rel_residual"] <= tol
     assert ext <= 1.5 * tol
     assert np.all(np.abs(lo) <= np.spacing(np.abs(hi)) / 2)
@@ -173,26 +178,27 @@ def test_double_double_solve_below_the_fp64_floor(torch_cuda, st, frame):
         mask[G:ny + G, G:nx + G] = False
         assert np.array_equal(hi[mask], u0[mask])
         assert np.all(lo[mask] == 0.0)
-    # the plain refinement of the same plan stops at the floor of an FP64 iterate
+    # the plain solve of the same plan stops at the floor of an FP64 iterate
     u2 = _dev(torch, u0)
     r2 = cj.solve(p, _dev(torch, f), u2)
     print("  FP64 iterate: status %s, relres %.3e" % (r2["status"], r2["rel_residual"]), flush=True)
     assert ext < r2["rel_residual"]
 
 
-def test_double_double_solve_large(torch_cuda):
+@pytest.mark.parametrize("precision", DD_PRECISIONS)
+def test_double_double_solve_large(torch_cuda, precision):
     """2047^2, 9-point: tol 1e-12, below the floor of an FP64 iterate there
     (about 2e-11)."""
     torch = torch_cuda
     n, st, tol = 2047, 9, 1e-12
     f = inputs.gaussian_bumps_rhs(n, n, seed=99)
-    p = cj.plan(n, n, st, tol, precision=cj.F32_REFINE)
+    p = cj.plan(n, n, st, tol, precision=precision)
     u = torch.zeros(n, n, dtype=torch.float64, device="cuda")
     lo = torch.zeros_like(u)
     r = cj.solve_dd(p, _dev(torch, f), u, lo)
     ext = cjm.relative_residual_ext(st, f, _host(u), _host(lo), n, n)
-    print("n %d: status %s, outer %d, FP32 sweeps %d, relres %.3e, oracle (extended) %.3e"
-          % (n, r["status"], r["cycles"], r["sweeps"], r["rel_residual"], ext), flush=True)
+    print("n %d precision %d: status %s, outer %d, sweeps %d, relres %.3e, oracle (extended) %.3e"
+          % (n, precision, r["status"], r["cycles"], r["sweeps"], r["rel_residual"], ext), flush=True)
     assert r["status"] == "ok"
     assert ext <= 1.5 * tol
 
@@ -202,16 +208,17 @@ def test_double_double_argument_errors(torch_cuda):
     n = 40
     f = _dev(torch, inputs.gaussian_bumps_rhs(n, n, seed=1))
     u = torch.zeros(n, n, dtype=torch.float64, device="cuda")
-    p64 = cj.plan(n, n, 9, 1e-10)
+    pj = cj.plan(n, n, 9, 1e-10, method=cj.JACOBI)
     with pytest.raises(cj.CJError) as e:
-        cj.solve_dd(p64, f, u, torch.zeros_like(u))
+        cj.solve_dd(pj, f, u, torch.zeros_like(u))
     assert e.value.code == cj.CJ_ERR_ARG
     p = cj.plan(n, n, 9, 1e-10, precision=cj.F32_REFINE)
     with pytest.raises(cj.CJError) as e:
         cj.solve_dd(p, f, u, u)
     assert e.value.code == cj.CJ_ERR_ARG
     # f = 0: u and u_lo come back zero
-    lo = torch.full_like(u, 3.0)
-    u.fill_(1.0)
-    r = cj.solve_dd(p, torch.zeros_like(f), u, lo)
-    assert r["status"] == "ok" and not bool(u.any()) and not bool(lo.any())
+    for q in (p, cj.plan(n, n, 9, 1e-10)):
+        lo = torch.full_like(u, 3.0)
+        u.fill_(1.0)
+        r = cj.solve_dd(q, torch.zeros_like(f), u, lo)
+        assert r["status"] == "ok" and not bool(u.any()) and not bool(lo.any())
