@@ -222,3 +222,31 @@ def test_double_double_argument_errors(torch_cuda):
         u.fill_(1.0)
         r = cj.solve_dd(q, torch.zeros_like(f), u, lo)
         assert r["status"] == "ok" and not bool(u.any()) and not bool(lo.any())
+
+
+@pytest.mark.parametrize("precision", DD_PRECISIONS)
+@pytest.mark.parametrize("st,frame", [(17, True), (17, False), (9, True)])
+def test_plain_solve_after_double_double_is_unchanged(torch_cuda, st, frame, precision):
+    """cj_solve_dd keeps the low parts in the plan's second iterate; a later
+    cj_solve and cj_sweeps on the same plan give the bits of a fresh plan."""
+    torch = torch_cuda
+    nx, ny, tol = 97, 83, 1e-9
+    f = _dev(torch, inputs.gaussian_bumps_rhs(nx, ny, seed=st))
+    bc = cj.BC_FRAME if frame else cj.BC_ZERO
+    if frame:
+        u0 = inputs.expxy_frame(nx, ny, inputs.frame_width(st))
+    else:
+        u0 = np.zeros((ny, nx))
+    used = cj.plan(nx, ny, st, tol, precision=precision, bc=bc)
+    fresh = cj.plan(nx, ny, st, tol, precision=precision, bc=bc)
+    u, lo = _dev(torch, u0), _dev(torch, u0)
+    cj.solve_dd(used, f, u, lo)
+    a, b = _dev(torch, u0), _dev(torch, u0)
+    ra = cj.solve(used, f, a)
+    rb = cj.solve(fresh, f, b)
+    assert (ra["status"], ra["cycles"]) == (rb["status"], rb["cycles"])
+    assert torch.equal(a, b)
+    a, b = _dev(torch, u0), _dev(torch, u0)
+    cj.sweeps(used, f, a, 11)
+    cj.sweeps(fresh, f, b, 11)
+    assert torch.equal(a, b)
