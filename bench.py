@@ -19,6 +19,9 @@ single_sweep_reference = the one-sweep-per-launch kernel on the same grid,
              timed with HIP events on the solve's stream (24 B per update).
 cpu_baseline = the CPU oracle's sweep loop on the same workload, for a bounded
              number of sweeps (about --cpu-seconds of host time).
+double_double_companion = one untimed-region solve of the same plan through
+             cj_solve_dd (FP64 cycles, double-double iterate), which can meet
+             a tolerance below the FP64 floor that stops the plain solve.
 """
 import argparse
 import hashlib
@@ -485,6 +488,8 @@ def main():
     ap.add_argument("--seed", type=int, default=None, help="RHS seed (default 1705 + stencil)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dd-companion", action="store_true",
+                    help="plain FP64 runs: skip the untimed double-double solve of the same plan")
     ap.add_argument("--tile-rows", type=str, default="0",
                     help="tile height of the blocked launches (0: the plan's default, tuned on large grids); "
                          "traffic probe: a comma-separated list, the first being the main one")
@@ -588,6 +593,21 @@ def main():
         if traffic:
             roofline["traffic_gbs"] = round(traffic / avg / 1e9, 1)
     single = None if (mixed or ny != n) else single_sweep_reference(cj, fd, n, st, tol)
+    dd_companion = None
+    if not mixed and not dd and not args.no_dd_companion:
+        # outside the timed region: the same plan through cj_solve_dd (FP64
+        # cycles, the iterate carried as a double-double), which can meet a
+        # tolerance below the FP64 floor that stops the plain solve
+        u2 = torch.zeros_like(u)
+        lo2 = torch.zeros_like(u)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()               # includes the first call's workspace allocation
+        r2 = cj.solve_dd(p, fd, u2, lo2)
+        torch.cuda.synchronize()
+        dd_companion = {"entry_point": "cj_solve_dd", "status": r2["status"], "rel_residual": r2["rel_residual"],
+                        "cycles": r2["cycles"], "sweeps": r2["sweeps"], "seconds": time.perf_counter() - ts,
+                        "rel_l2_vs_plain": float(torch.linalg.norm(u2 - u) / torch.linalg.norm(u))}
+        del u2, lo2
     ref64 = None
     if mixed and args.reference_f64:
         p64 = cj.plan(n, ny, st, tol)
@@ -637,6 +657,7 @@ def main():
         "roofline": roofline,
         "single_sweep_reference": single,
         "f64_reference": ref64,
+        "double_double_companion": dd_companion,
         "cpu_baseline": cpu,
     }
     if cpu is not None:
