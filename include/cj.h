@@ -177,7 +177,8 @@ cj_status cj_plan_launch_info(cj_plan_t p, int* sweeps_per_launch, int* tile_row
  * prescribed tolerance, §3.4; mid-cycle iterates are not meaningful).  Stops
  * with CJ_OK when it is <= tol; with CJ_STAGNATED when, at or after the
  * predicted cycle count, a cycle fails to halve it (the FP64 floor of large
- * grids); with CJ_ERR_NOT_CONVERGED after max_cycles.  In each of these cases
+ * grids; cj_solve_dd meets tolerances below it); with CJ_ERR_NOT_CONVERGED
+ * after max_cycles.  In each of these cases
  * u holds the last cycle-end iterate.  f = 0 gives u = 0 and CJ_OK.
  * CJ_ERR_NONFINITE if f or an iterate has a NaN or Inf.  The device
  * workspace is allocated on the first call and kept by the plan.
