@@ -250,3 +250,22 @@ def test_plain_solve_after_double_double_is_unchanged(torch_cuda, st, frame, pre
     cj.sweeps(used, f, a, 11)
     cj.sweeps(fresh, f, b, 11)
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("precision", DD_PRECISIONS)
+def test_double_double_not_converged_returns_the_last_iterate(torch_cuda, precision):
+    """max_cycles outer steps without meeting tol: status not_converged, and the
+    pair returned is the iterate whose residual was reported (checked by the
+    oracle's extended-precision residual)."""
+    torch = torch_cuda
+    nx, ny, st = 150, 131, 9
+    f = inputs.gaussian_bumps_rhs(nx, ny, seed=8)
+    p = cj.plan(nx, ny, st, 1e-15, precision=precision, max_cycles=1)
+    u = torch.zeros(ny, nx, dtype=torch.float64, device="cuda")
+    lo = torch.zeros_like(u)
+    r = cj.solve_dd(p, _dev(torch, f), u, lo)
+    ext = cjm.relative_residual_ext(st, f, _host(u), _host(lo), nx, ny)
+    print("precision %d: status %s, outer %d, relres %.6e, oracle (extended) %.6e"
+          % (precision, r["status"], r["cycles"], r["rel_residual"], ext), flush=True)
+    assert r["status"] == "not_converged" and r["cycles"] == 1
+    assert abs(ext - r["rel_residual"]) <= 1e-6 * ext + 1e-15
