@@ -101,3 +101,35 @@ def test_random_fp32_blocked_sweeps_bitwise(torch_cuda, seed):
     assert pk.sweeps_per_launch == K
     cj.sweeps(pk, _dev(torch, f), blk, n)
     assert np.array_equal(_host(blk), _host(one))
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_random_double_double_solves(torch_cuda, seed):
+    """cj_solve_dd on seeded random grids, stencils, data and inner precisions:
+    the oracle's extended-precision residual of u + u_lo meets the tolerance
+    (below the FP64 floor of the grid) and u_lo is a low part."""
+    torch = torch_cuda
+    rng = np.random.default_rng(3000 + seed)
+    nx, ny = int(rng.integers(1, 220)), int(rng.integers(1, 160))
+    st = int(rng.choice([5, 9, 17]))
+    frame = bool(rng.integers(0, 2))
+    precision = cj.F64 if rng.integers(0, 2) else cj.F32_REFINE
+    tol = 1e-14
+    print("case seed %d: %dx%d st %d frame %d precision %d" % (seed, nx, ny, st, frame, precision), flush=True)
+    f = inputs.gaussian_bumps_rhs(nx, ny, seed=seed)
+    bc = cj.BC_FRAME if frame else cj.BC_ZERO
+    if frame:
+        u0 = inputs.expxy_frame(nx, ny, inputs.frame_width(st))
+    else:
+        u0 = np.zeros((ny, nx))
+    p = cj.plan(nx, ny, st, tol, precision=precision, bc=bc, max_cycles=60)
+    u = _dev(torch, u0)
+    lo = torch.zeros_like(u)
+    r = cj.solve_dd(p, _dev(torch, f), u, lo)
+    hi, lo = _host(u), _host(lo)
+    ext = cjm.relative_residual_ext(st, f, hi, lo, nx, ny, bc=cjm.BC_FRAME if frame else cjm.BC_ZERO)
+    print("  status %s, outer %d, relres %.3e, oracle (extended) %.3e" % (r["status"], r["cycles"],
+                                                                          r["rel_residual"], ext), flush=True)
+    assert r["status"] == "ok"
+    assert ext <= 1.5 * tol
+    assert np.all(np.abs(lo) <= np.spacing(np.abs(hi)) / 2)
