@@ -147,7 +147,7 @@ DD_PRECISIONS = [pytest.param(cj.F32_REFINE, id="f32inner"), pytest.param(cj.F64
 @pytest.mark.parametrize("frame", [False, True])
 def test_double_double_solve_below_the_fp64_floor(torch_cuda, st, frame, precision):
     """cj_solve_dd carries the iterate as u + u_lo: it meets a tolerance far
-    below what an FP64 iterate can reach, judged by the oracle's residual of
+    below what an FP64 iterate can reach, measured by the oracle's residual of
     u + u_lo in extended precision; u_lo is the low part (|u_lo| <= ulp(u)/2),
     the frame comes back as given and u_lo's frame is zero.  Inner FP32 cycles
     (refinement plans) and FP64 cycles (FP64 plans)."""
