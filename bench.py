@@ -7,21 +7,29 @@ sweeps with the fused cycle-end residual test, stage-out) of the workload
   Dirichlet data, RHS = 16 seeded Gaussian bumps, tol = 1e-10 relative residual,
 with f already resident in HBM.  Prints one JSON line.
 
-value      = grid-point updates / s over the timed steps (updates = nx*ny*cycles*M)
+value      = grid-point updates / s of the plain FP64 solve over the timed steps
+             (updates = nx*ny*cycles*M).  On this grid the plain solve stops at
+             the floor of an FP64 iterate (status stagnated, about 2e-9):
+             time_to_floor_p50/p99 are its times.
+double_double_leg = the same plan through cj_solve_dd (FP64 cycles, the
+             iterate carried as a double-double), timed over the same number of
+             steps after a warm-up that allocates its workspace; it meets the
+             tolerance, and time_to_tol_p50/p99 are its times.
+fp64_floor = the residual of the exact discrete solution rounded to FP64
+             (oracle: sine-transform solve, residual in FP64 and in extended
+             precision), beside the plain solve's stagnation level.
 roofline   = the dominant kernel, the temporally blocked sweep (K sweeps per
-             launch): algorithmic bytes per launch = 24 B per grid-point update
-             (read u, read g, write u', FP64) x K updates x nx*ny points,
-             divided by its average launch duration (timed inside the library
-             with HIP events on the solve's stream), against 8 TB/s HBM.  With
-             K > 1 a launch touches HBM once for K updates, so frac can exceed 1;
-             `traffic` (rocprofv3 counters) gives the bytes actually moved.
+             launch), timed inside the library with HIP events on the solve's
+             stream: algorithmic bytes per launch = 24 B per grid point (read
+             u, read g, write u', FP64; 24/K B per update) over its average
+             launch duration, against 8 TB/s HBM.  effective_frac counts 24 B
+             per update (one HBM pass per sweep) and can exceed 1; traffic
+             (rocprofv3 counters) gives the bytes actually moved.
 single_sweep_reference = the one-sweep-per-launch kernel on the same grid,
              timed with HIP events on the solve's stream (24 B per update).
-cpu_baseline = the CPU oracle's sweep loop on the same workload, for a bounded
-             number of sweeps (about --cpu-seconds of host time).
-double_double_companion = one untimed-region solve of the same plan through
-             cj_solve_dd (FP64 cycles, double-double iterate), which can meet
-             a tolerance below the FP64 floor that stops the plain solve.
+cpu_baseline = the CPU oracle's sweep loop on the same workload (built with
+             -march=native on this host), one thread and all threads, each for
+             about --cpu-seconds; the time to tolerance is extrapolated.
 """
 import argparse
 import hashlib
@@ -125,25 +133,94 @@ def traffic_probe(n, st, tol, rows=(0,), launches=4):
                       "single_launches": launches, "geometries": geoms}), flush=True)
 
 
-def cpu_baseline(f, n, stencil, tol, budget_s):
-    from oracle import cjm
-    import numpy as np
-    p = cjm.plan(n, n, stencil, tol)
-    a = cjm.pad(np.zeros((n, n)), n, n)
-    b = np.zeros_like(a)
-    k = 0
-    t0 = time.perf_counter()
-    while True:
-        cjm.sweep(p, f, a, b, p.weights[k % p.M])
-        a, b = b, a
-        k += 1
-        if k >= 2 and time.perf_counter() - t0 >= budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": n * n * k / dt, "unit": "grid-point updates/s", "cores": cjm.threads(),
+_CPU_SWEEP_TIMER = r"""
+import json, sys, time
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+from oracle import cjm
+from paper_1705_00103_amd import inputs
+nx, ny, st, seed = (int(v) for v in sys.argv[2:6])
+tol, budget = float(sys.argv[6]), float(sys.argv[7])
+f = inputs.gaussian_bumps_rhs(nx, ny, seed=seed)
+p = cjm.plan(nx, ny, st, tol)
+a = cjm.pad(np.zeros((ny, nx)), nx, ny)
+b = np.zeros_like(a)
+k, t0 = 0, time.perf_counter()
+while k < 2 or time.perf_counter() - t0 < budget:
+    cjm.sweep(p, f, a, b, p.weights[k % p.M])
+    a, b = b, a
+    k += 1
+print(json.dumps({"threads": cjm.threads(), "sweeps": k, "seconds": time.perf_counter() - t0, "M": p.M}))
+"""
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(n, ny, stencil, tol, seed, budget_s, sweeps_per_solve):
+    """The oracle's sweep loop on the same workload, built for this host's CPU
+    (-march=native), from u = 0 along the solve's own schedule: one thread (the
+    analogue of the paper's serial code) and all threads OpenMP gives it, each
+    in a child process for about budget_s seconds.  A bounded window of the
+    first cycle, so the time to tolerance is extrapolated from the sweep rate."""
+    import subprocess
+    from oracle import build as obuild
+    build = "-march=native"
+    try:
+        obuild.build(native=True)
+    except (subprocess.CalledProcessError, OSError):
+        build = "portable (the -march=native build failed)"
+    legs = {}
+    for label, threads in (("single_thread", "1"), ("all_cores", None)):
+        env = dict(os.environ)
+        if build == "-march=native":
+            env["CJ_ORACLE_NATIVE"] = "1"
+        if threads:
+            env["OMP_NUM_THREADS"] = threads
+        outp = subprocess.run([sys.executable, "-c", _CPU_SWEEP_TIMER, ROOT, str(n), str(ny), str(stencil),
+                               str(seed), repr(tol), str(budget_s)],
+                              env=env, check=True, capture_output=True, text=True).stdout
+        r = json.loads(outp.strip().splitlines()[-1])
+        r["updates_per_s"] = float(n) * ny * r["sweeps"] / r["seconds"]
+        r["time_to_tol_s_extrapolated"] = sweeps_per_solve * r["seconds"] / r["sweeps"]
+        legs[label] = r
+    allc, one = legs["all_cores"], legs["single_thread"]
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    return {"value": allc["updates_per_s"], "unit": "grid-point updates/s", "cores": allc["threads"],
             "kind": "oracle",
-            "sample": "%d sweeps of the %dx%d %d-point schedule from u=0 (oracle sweep loop, FP64, "
-                      "OpenMP over rows), %.1f s" % (k, n, n, stencil, dt)}
+            "sample": "%d sweeps (%.3f of one %d-sweep cycle) of the %dx%d %d-point schedule from u=0, oracle sweep "
+                      "loop (FP64, %s, OpenMP over rows), %.1f s on %d threads; extrapolated to the solve's %d "
+                      "sweeps" % (allc["sweeps"], allc["sweeps"] / allc["M"], allc["M"], n, ny, stencil, build,
+                                  allc["seconds"], allc["threads"], sweeps_per_solve),
+            "extrapolated": True,
+            "time_to_tol_s_extrapolated": allc["time_to_tol_s_extrapolated"],
+            "single_thread": {"value": one["updates_per_s"], "cores": 1, "sweeps": one["sweeps"],
+                              "seconds": one["seconds"],
+                              "time_to_tol_s_extrapolated": one["time_to_tol_s_extrapolated"]},
+            "cpu_model": _cpu_model(), "nproc": nproc, "build": build}
+
+
+def fp64_floor(f, n, ny, stencil):
+    """The residual an FP64 array can hold on this grid: the relative residual of
+    the exact discrete solution (type-I sine transform in FP64) after its
+    rounding to FP64, evaluated by the oracle in FP64 and in extended precision."""
+    import numpy as np
+    from oracle import cjm, dense
+    taps, s = cjm.taps(stencil)
+    u = dense.dst_solve(taps, s, f, n, ny, cjm.spacing(n, ny))
+    return {"dst_solution_relres_fp64_eval": cjm.relative_residual(stencil, f, u, n, ny),
+            "dst_solution_relres_ext_eval": cjm.relative_residual_ext(stencil, f, u, np.zeros_like(u), n, ny)}
 
 
 def run_batch(args):
@@ -486,10 +563,12 @@ def main():
     ap.add_argument("--stencil", type=int, default=9, choices=(5, 9, 17))
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--seed", type=int, default=None, help="RHS seed (default 1705 + stencil)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="host seconds of each CPU-baseline leg (one thread, all threads)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-dd-companion", action="store_true",
-                    help="plain FP64 runs: skip the untimed double-double solve of the same plan")
+    ap.add_argument("--no-dd-leg", action="store_true",
+                    help="plain FP64 runs: skip the timed double-double solves of the same plan (cj_solve_dd, "
+                         "which meets tolerances below the FP64 floor; its times are the time to tolerance)")
     ap.add_argument("--tile-rows", type=str, default="0",
                     help="tile height of the blocked launches (0: the plan's default, tuned on large grids); "
                          "traffic probe: a comma-separated list, the first being the main one")
@@ -581,32 +660,65 @@ def main():
     roofline = None
     if launches > 0:
         avg = sweep_s / launches
-        algo = bpu * K * n * ny
+        # a launch of K sweeps must read u and g and write u' once per grid
+        # point: bpu bytes per point, i.e. bpu / K per grid-point update
+        algo = bpu * n * ny
         achieved = algo / avg / 1e9
+        effective = bpu * K * n * ny / avg / 1e9
         traffic = None if (mixed or ny != n) else measured_traffic(n, st, K, p.tile_rows)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "kernel": "sweepk_kernel<%s, %d, K=%d, no-norm>" % ("float" if mixed else "double", st, K),
                     "sweeps_per_launch": K,
                     "avg_launch_us": round(avg * 1e6, 2), "algorithmic_bytes_per_launch": algo,
-                    "compulsory_hbm_bytes_per_launch": bpu * n * ny}
+                    "algorithmic_bytes_per_update": bpu / K,
+                    "effective_achieved": round(effective, 1),
+                    "effective_frac": round(effective / HBM_PEAK_GBS, 4),
+                    "effective_note": "%g B per update (one HBM pass per sweep) x K updates per launch; above 1 "
+                                      "means the K-sweep launch does more updates than a one-sweep-per-launch "
+                                      "kernel could at the HBM peak" % bpu}
         if traffic:
             roofline["traffic_gbs"] = round(traffic / avg / 1e9, 1)
+            roofline["traffic_frac"] = round(traffic / avg / 1e9 / HBM_PEAK_GBS, 4)
     single = None if (mixed or ny != n) else single_sweep_reference(cj, fd, n, st, tol)
-    dd_companion = None
-    if not mixed and not dd and not args.no_dd_companion:
-        # outside the timed region: the same plan through cj_solve_dd (FP64
-        # cycles, the iterate carried as a double-double), which can meet a
-        # tolerance below the FP64 floor that stops the plain solve
+
+    lat_ms = sorted(x * 1e3 for x in lat)
+    p50 = float(np.percentile(lat_ms, 50))
+    p99 = float(np.percentile(lat_ms, 99))
+    last = res[-1]
+
+    # The plain FP64 solve stops at the floor of an FP64 iterate on large grids
+    # (1.98e-9 at 8192^2).  The same plan through cj_solve_dd (FP64 cycles, the
+    # iterate carried as a double-double) meets the tolerance: it is timed over
+    # the same number of steps (its workspace allocated in its warm-up), and
+    # its times are the time to tolerance.
+    dd_leg = None
+    if not mixed and not dd and not args.no_dd_leg:
         u2 = torch.zeros_like(u)
         lo2 = torch.zeros_like(u)
+        u2.zero_()
+        cj.solve_dd(p, fd, u2, lo2)            # warm-up: allocates the double-double workspace
         torch.cuda.synchronize()
-        ts = time.perf_counter()               # includes the first call's workspace allocation
-        r2 = cj.solve_dd(p, fd, u2, lo2)
-        torch.cuda.synchronize()
-        dd_companion = {"entry_point": "cj_solve_dd", "status": r2["status"], "rel_residual": r2["rel_residual"],
-                        "cycles": r2["cycles"], "sweeps": r2["sweeps"], "seconds": time.perf_counter() - ts,
-                        "rel_l2_vs_plain": float(torch.linalg.norm(u2 - u) / torch.linalg.norm(u))}
+        lat_dd, res_dd = [], []
+        td0 = time.perf_counter()
+        for _ in range(args.steps):
+            ts = time.perf_counter()
+            u2.zero_()
+            r2 = cj.solve_dd(p, fd, u2, lo2)
+            torch.cuda.synchronize()
+            lat_dd.append(time.perf_counter() - ts)
+            res_dd.append(r2)
+        td1 = time.perf_counter()
+        r2 = res_dd[-1]
+        ldd = sorted(x * 1e3 for x in lat_dd)
+        dd_leg = {"entry_point": "cj_solve_dd (FP64 cycles of the same plan, double-double iterate)",
+                  "steps": args.steps, "status": r2["status"], "rel_residual": r2["rel_residual"],
+                  "cycles": r2["cycles"], "sweeps": r2["sweeps"],
+                  "time_to_tol_p50_ms": float(np.percentile(ldd, 50)),
+                  "time_to_tol_p99_ms": float(np.percentile(ldd, 99)),
+                  "ms_per_step": (td1 - td0) / args.steps * 1e3,
+                  "updates_per_s": float(n) * ny * sum(r["sweeps"] for r in res_dd) / (td1 - td0),
+                  "rel_l2_vs_plain": float(torch.linalg.norm(u2 - u) / torch.linalg.norm(u))}
         del u2, lo2
     ref64 = None
     if mixed and args.reference_f64:
@@ -618,14 +730,24 @@ def main():
                  "f64_seconds": r64["seconds"]}
         p64.destroy()
 
-    lat_ms = sorted(x * 1e3 for x in lat)
-    p50 = float(np.percentile(lat_ms, 50))
-    p99 = float(np.percentile(lat_ms, 99))
-    last = res[-1]
-
     cpu = None
-    if not args.no_cpu_baseline and not mixed and ny == n:
-        cpu = cpu_baseline(f, n, st, tol, args.cpu_seconds)
+    floor = None
+    if not args.no_cpu_baseline and not mixed:
+        cpu = cpu_baseline(n, ny, st, tol, seed, args.cpu_seconds, last["sweeps"])
+        floor = fp64_floor(f, n, ny, st)
+
+    # time to tolerance: the solve that meets tol (status ok) at the metric's
+    # tolerance; the plain solve's time to its stagnation level is reported
+    # beside it as time_to_floor
+    if dd_leg is not None and dd_leg["status"] == "ok":
+        ttt = {"time_to_tol_p50_ms": dd_leg["time_to_tol_p50_ms"], "time_to_tol_p99_ms": dd_leg["time_to_tol_p99_ms"],
+               "time_to_tol_from": "double_double_leg", "effective_tol": tol}
+    elif last["status"] == "ok":
+        ttt = {"time_to_tol_p50_ms": p50, "time_to_tol_p99_ms": p99, "time_to_tol_from": "timed steps",
+               "effective_tol": tol}
+    else:
+        ttt = {"time_to_tol_p50_ms": None, "time_to_tol_p99_ms": None,
+               "time_to_tol_from": "not met (status %s)" % last["status"], "effective_tol": last["rel_residual"]}
 
     out = {
         "metric": METRIC,
@@ -647,21 +769,23 @@ def main():
             "cycles_pred": p.cycles_pred, "sweeps_per_launch": K, "tile_rows": p.tile_rows,
             "parallelism": "single-gpu",
         },
-        "time_to_tol_p50_ms": p50,
-        "time_to_tol_p99_ms": p99,
+        **ttt,
+        "time_to_floor_p50_ms": p50 if last["status"] == "stagnated" else None,
+        "time_to_floor_p99_ms": p99 if last["status"] == "stagnated" else None,
         "solve_status": last["status"],
         "cycles": last["cycles"],
         "sweeps_per_solve": last["sweeps"],
         "rel_residual": last["rel_residual"],
-        "effective_tol": last["rel_residual"] if last["status"] == "stagnated" else tol,
+        "fp64_floor": floor,
         "roofline": roofline,
         "single_sweep_reference": single,
         "f64_reference": ref64,
-        "double_double_companion": dd_companion,
+        "double_double_leg": dd_leg,
         "cpu_baseline": cpu,
     }
     if cpu is not None:
         out["gpu_over_cpu_updates"] = value / cpu["value"]
+        out["gpu_over_cpu_single_thread_updates"] = value / cpu["single_thread"]["value"]
     print(json.dumps(out), flush=True)
 
 

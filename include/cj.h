@@ -90,9 +90,19 @@ typedef enum { CJ_METHOD_CHEBYSHEV = 0, CJ_METHOD_JACOBI = 1 } cj_method;
  *   of FP32 weighted sweeps from d = 0 (the same Chebyshev schedule, weights
  *   rounded to FP32), and adds d to u in FP64.  The stopping test is the FP64
  *   relative residual.  Each FP32 sweep moves half the bytes of an FP64 one;
- *   the contraction per outer step is limited to about eps32 * kmax / kmin,
- *   so large grids may stagnate (reported as CJ_STAGNATED). */
+ *   the contraction per outer step is limited by eps32 * kmax / kmin, so on
+ *   grids where that product is large the inner cycles run in FP64 instead
+ *   (cj_inner_precision). */
 typedef enum { CJ_PRECISION_F64 = 0, CJ_PRECISION_F32_REFINE = 1 } cj_precision;
+
+/* Inner cycles of a CJ_PRECISION_F32_REFINE plan (cj_options.inner_precision).
+ * CJ_INNER_AUTO: FP32, unless eps32 * kappa_max / kappa_min > 4 (for example
+ *   16384^2, 9-point: 8.6; 8192^2: 2.2), where FP32 cycles barely contract
+ *   the correction and FP64 cycles of the plan's schedule take their place.
+ * CJ_INNER_F32, CJ_INNER_F64: forced.  With FP64 inner cycles the plan sweeps
+ *   in FP64 everywhere (cj_sweeps, cj_plan_launch_info) and its workspace
+ *   holds three more padded FP64 arrays instead of the FP32 ones. */
+typedef enum { CJ_INNER_AUTO = 0, CJ_INNER_F32 = 1, CJ_INNER_F64 = 2 } cj_inner_precision;
 
 /* Tuning and schedule options for cj_plan_ex.  Zero means "automatic". */
 typedef struct {
@@ -120,7 +130,9 @@ typedef struct {
                                   graph; 0 = automatic (grids of at most 2^22 points, where
                                   launch overhead matters), 1 = always, -1 = never */
     int    method;             /* cj_method; 0 = CJ_METHOD_CHEBYSHEV */
-    int    reserved[4];        /* must be zero */
+    int    inner_precision;    /* cj_inner_precision of a CJ_PRECISION_F32_REFINE plan; must be
+                                  0 otherwise */
+    int    reserved[3];        /* must be zero */
 } cj_options;
 
 /* Outcome of a solve. */
@@ -156,7 +168,7 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol,
 /* Reads a plan.  Any output pointer may be NULL.  *weights_host points to the
  * plan's M weights in applied order (owned by the plan, valid until destroy);
  * for CJ_PRECISION_F32_REFINE plans M, cycles_pred and the weights are those
- * of the inner FP32 cycle.
+ * of the inner cycle.
  * *workspace_bytes is the device memory cj_solve allocates on first use:
  * two padded iterates, the padded scaled right-hand side, the weights and
  * the reduction buffers. */
@@ -209,8 +221,9 @@ cj_status cj_solve_dd(cj_plan_t p, const double* f, double* u, double* u_lo, voi
 /* Applies the first n_sweeps weighted sweeps of the plan's schedule (weights
  * taken cyclically) to the guess u, with no residual test; u is overwritten.
  * Same kernels and launch configuration as cj_solve.  n_sweeps >= 0.
- * CJ_PRECISION_F32_REFINE plans sweep in FP32: u and D^{-1} f are rounded to
- * FP32, the sweeps run in FP32 and the result is widened back. */
+ * CJ_PRECISION_F32_REFINE plans with FP32 inner cycles sweep in FP32: u and
+ * D^{-1} f are rounded to FP32, the sweeps run in FP32 and the result is
+ * widened back. */
 cj_status cj_sweeps(cj_plan_t p, const double* f, double* u, long long n_sweeps, void* stream);
 
 /* *rel_residual = ||f - A u||_2 / ||f||_2 (0 when f = 0; frame: over the

@@ -69,13 +69,16 @@ BC_ZERO, BC_FRAME = 0, 1
 
 
 def lib():
-    """The compiled loops of cj_oracle.c (built on first use if absent)."""
+    """The compiled loops of cj_oracle.c (built on first use if absent).  With
+    CJ_ORACLE_NATIVE=1 in the environment, the build for this host's CPU
+    (-march=native), used to time the oracle as a CPU baseline."""
     global _LIB
     if _LIB is None:
-        path = os.path.join(_HERE, "_cj_oracle.so")
+        native = os.environ.get("CJ_ORACLE_NATIVE") == "1"
+        path = os.path.join(_HERE, "_cj_oracle_native.so" if native else "_cj_oracle.so")
         if not os.path.exists(path):
             from oracle import build as _b
-            _b.build()
+            _b.build(native=native)
         L = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)

@@ -34,6 +34,9 @@ BC_ZERO = 0         # CJ_BC_DIRICHLET0
 BC_FRAME = 1        # CJ_BC_DIRICHLET_FRAME: u carries the boundary data in a frame
 CHEBYSHEV = 0       # CJ_METHOD_CHEBYSHEV
 JACOBI = 1          # CJ_METHOD_JACOBI
+INNER_AUTO = 0      # CJ_INNER_AUTO: inner cycles of a refinement plan chosen from eps32 * kmax / kmin
+INNER_F32 = 1       # CJ_INNER_F32
+INNER_F64 = 2       # CJ_INNER_F64
 
 STATUS_NAMES = {
     CJ_OK: "ok", CJ_STAGNATED: "stagnated", CJ_ERR_ARG: "arg", CJ_ERR_NOMEM: "nomem",
@@ -43,7 +46,8 @@ STATUS_NAMES = {
 
 # Function names declared in include/cj.h (checked against the header by the tests).
 EXPORTS = ("cj_options_init", "cj_plan", "cj_plan_ex", "cj_plan_info", "cj_plan_launch_info", "cj_solve",
-           "cj_solve_dd", "cj_sweeps", "cj_residual", "cj_apply", "cj_plan_destroy", "cj_status_string", "cj_last_error",
+           "cj_solve_dd", "cj_sweeps", "cj_residual", "cj_apply", "cj_plan_destroy",
+           "cj_status_string", "cj_last_error",
            "cj_batch_create", "cj_batch_info", "cj_batch_solve", "cj_batch_destroy",
            "cj_server_create", "cj_server_submit", "cj_server_step", "cj_server_stats", "cj_server_destroy")
 
@@ -52,7 +56,8 @@ class Options(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int), ("max_cycles", ctypes.c_int),
                 ("sweeps_per_launch", ctypes.c_int), ("tile_rows", ctypes.c_int),
                 ("h", ctypes.c_double), ("precision", ctypes.c_int), ("inner_M", ctypes.c_int),
-                ("graph", ctypes.c_int), ("method", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
+                ("graph", ctypes.c_int), ("method", ctypes.c_int), ("inner_precision", ctypes.c_int),
+                ("reserved", ctypes.c_int * 3)]
 
 
 class Result(ctypes.Structure):
@@ -164,12 +169,14 @@ class Plan:
     """Owns a cj_plan_t.  Attributes mirror cj_plan_info."""
 
     def __init__(self, nx, ny, stencil=9, tol=1e-10, M=0, max_cycles=0, sweeps_per_launch=0,
-                 tile_rows=0, h=0.0, bc=BC_ZERO, precision=F64, inner_M=0, graph=0, method=CHEBYSHEV):
+                 tile_rows=0, h=0.0, bc=BC_ZERO, precision=F64, inner_M=0, graph=0, method=CHEBYSHEV,
+                 inner_precision=INNER_AUTO):
         L = lib()
         o = Options()
         L.cj_options_init(ctypes.byref(o))
         o.M, o.max_cycles, o.sweeps_per_launch, o.tile_rows, o.h = M, max_cycles, sweeps_per_launch, tile_rows, h
         o.precision, o.inner_M, o.graph, o.method = precision, inner_M, graph, method
+        o.inner_precision = inner_precision
         self.precision, self.bc, self.method = precision, bc, method
         # width of u's boundary frame (CJ_BC_DIRICHLET_FRAME)
         self.frame = (2 if stencil == 17 else 1) if bc == BC_FRAME else 0

@@ -151,7 +151,7 @@ hipError_t launch_ir_residual(int stencil, const Layout& L, const Tiles& T, cons
 // double-double.
 hipError_t launch_ir_correct(const Layout& L, const Layout& L32, double* u, double* lo, const float* d,
                              hipStream_t stream);
-// (u, lo) += d (FP64, layout L) as a double-double; lo must be non-null.
+// u += d (FP64, layout L); with lo non-null, (u, lo) += d as a double-double.
 hipError_t launch_ir_correct(const Layout& L, double* u, double* lo, const double* d, hipStream_t stream);
 // Padded-frame conversions between the FP64 and FP32 layouts.
 hipError_t launch_to_f32(const Layout& L, const Layout& L32, const double* src, float* dst, hipStream_t stream);

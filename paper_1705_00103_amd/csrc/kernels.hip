@@ -752,13 +752,14 @@ __global__ __launch_bounds__(256) void ir_residual_kernel(const double* __restri
 // Dirichlet ring of d is zero and its outer ring holds the reflection of its
 // interior (homogeneous 17-point data) or zero (boundary data), so u keeps
 // its boundary exactly.
-__global__ __launch_bounds__(256) void ir_correct_kernel(double* __restrict__ u, const float* __restrict__ d,
-                                                         int nx, int ny, int pitch, int pitch32, int bx) {
+template <typename TD>
+__global__ __launch_bounds__(256) void ir_correct_kernel(double* __restrict__ u, const TD* __restrict__ d,
+                                                         int nx, int ny, int pitch, int pitchd, int bx) {
     const int x = (int)(blockIdx.x % bx) * 256 + (int)threadIdx.x - 1;
     const int y = (int)(blockIdx.x / bx) - 1;
     if (x > nx + 2 || y > ny + 2) return;
     double* p = u + at<double>(pitch, x, y);
-    *p = *p + (double)d[at<float>(pitch32, x, y)];
+    *p = *p + (double)d[at<TD>(pitchd, x, y)];
 }
 
 // (hi, lo) += d over the whole padded frame, as a double-double: TwoSum of
@@ -1115,11 +1116,9 @@ hipError_t ir_correct_launch(const Layout& L, const Layout& LD, double* u, doubl
     if (lo)
         hipLaunchKernelGGL((ir_correct_dd_kernel<TD>), dim3(nb), dim3(256), 0, stream, u, lo, d, L.nx, L.ny,
                            L.pitch, LD.pitch, bx);
-    else if constexpr (sizeof(TD) == 4)
-        hipLaunchKernelGGL(ir_correct_kernel, dim3(nb), dim3(256), 0, stream, u, d, L.nx, L.ny, L.pitch, LD.pitch,
-                           bx);
     else
-        return hipErrorInvalidValue;
+        hipLaunchKernelGGL((ir_correct_kernel<TD>), dim3(nb), dim3(256), 0, stream, u, d, L.nx, L.ny, L.pitch,
+                           LD.pitch, bx);
     return hipGetLastError();
 }
 

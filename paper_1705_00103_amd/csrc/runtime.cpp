@@ -62,6 +62,10 @@ double centre_over_s(int stencil) {
 
 int radius(int stencil) { return stencil == 17 ? 2 : 1; }
 
+// Refinement plans switch their inner cycles from FP32 to FP64 above this
+// value of eps32 * kappa_max / kappa_min (CJ_INNER_AUTO).
+constexpr double kInnerF64Above = 4.0;
+
 }  // namespace
 
 struct cj_plan_s {
@@ -113,11 +117,17 @@ struct cj_plan_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     long long graph_launches = 0;
+    // Refinement plans whose inner cycles run in FP64: chosen when
+    // eps32 * kappa_max / kappa_min is large (cj_plan_ex), where FP32 cycles
+    // contract too little per outer step.
+    bool inner_f64 = false;
     bool mixed() const { return precision == CJ_PRECISION_F32_REFINE; }
+    bool f32_inner() const { return mixed() && !inner_f64; }
     size_t workspace_bytes() const {
         size_t b = 3 * L.elems * sizeof(double) + (size_t)s.M * sizeof(double) +
                    ((size_t)n_partials() + 64) * sizeof(double);
-        if (mixed()) b += 3 * L32.elems * sizeof(float) + w32_all.size() * sizeof(float);
+        if (f32_inner()) b += 3 * L32.elems * sizeof(float) + w32_all.size() * sizeof(float);
+        if (inner_f64) b += 3 * L.elems * sizeof(double);
         return b;
     }
     int n_partials() const {
@@ -185,7 +195,7 @@ cj_status ensure_device(cj_plan_s* p, hipStream_t stream) {
     if (e == hipSuccess) e = hipHostMalloc((void**)&p->host_slot, 64 * sizeof(double), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreate(&p->ev[0]);
     if (e == hipSuccess) e = hipEventCreate(&p->ev[1]);
-    if (p->mixed()) {
+    if (p->f32_inner()) {
         const size_t b32 = p->L32.elems * sizeof(float);
         if (e == hipSuccess) e = hipMalloc((void**)&p->R32, b32);
         if (e == hipSuccess) e = hipMalloc((void**)&p->D1, b32);
@@ -199,7 +209,7 @@ cj_status ensure_device(cj_plan_s* p, hipStream_t stream) {
                     std::string("workspace allocation: ") + hipGetErrorString(e));
     }
     CJ_HIP(hipMemcpyAsync(p->W, p->s.w.data(), (size_t)p->s.M * sizeof(double), hipMemcpyHostToDevice, stream));
-    if (p->mixed()) {
+    if (p->f32_inner()) {
         // the corrections' Dirichlet rings stay zero for the life of the plan
         CJ_HIP(hipMemsetAsync(p->D1, 0, p->L32.elems * sizeof(float), stream));
         CJ_HIP(hipMemsetAsync(p->D2, 0, p->L32.elems * sizeof(float), stream));
@@ -326,7 +336,7 @@ cj_status capture_cycle(cj_plan_s* p, long long k0) {
 cj_status tune_tile_rows(cj_plan_s* p, hipStream_t stream) {
     if (!p->tune_rows || p->rows_tuned) return CJ_OK;
     p->rows_tuned = true;
-    const bool mixed = p->mixed();
+    const bool mixed = p->f32_inner();
     const int K = mixed ? p->K32 : p->K;
     if (K <= 1) return CJ_OK;
     const int R = radius(p->s.stencil);
@@ -494,7 +504,7 @@ cj_status solve_f64(cj_plan_s* p, double gnorm, hipStream_t stream, cj_result* r
 // only) corrects with one FP64 cycle of its own schedule per outer step
 // instead, on the buffers R64, E1 and E2.
 cj_status solve_refine(cj_plan_s* p, double gnorm, hipStream_t stream, cj_result* r, double* lo) {
-    const bool f64 = !p->mixed();
+    const bool f64 = !p->f32_inner();
     cj_status st;
     int m = p->sin.M;
     double prev = 0.0;
@@ -592,7 +602,10 @@ cj_status solve_common(cj_plan_t p, const double* f, double* u, double* u_lo, vo
     }
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     if ((st = ensure_device(p, stream)) != CJ_OK) return finish(st);
-    if (dd && !p->mixed() && !p->R64) {
+    // FP64 correction cycles (double-double solves of FP64 plans, refinement
+    // plans with FP64 inner cycles) need the inner right-hand side and two
+    // correction iterates
+    if ((dd || p->mixed()) && !p->f32_inner() && !p->R64) {
         const size_t bytes = p->L.elems * sizeof(double);
         hipError_t e = hipMalloc((void**)&p->R64, bytes);
         if (e == hipSuccess) e = hipMalloc((void**)&p->E1, bytes);
@@ -676,7 +689,29 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol, const cj_o
     if (o.precision != CJ_PRECISION_F64 && o.precision != CJ_PRECISION_F32_REFINE)
         return fail(CJ_ERR_ARG, "precision must be CJ_PRECISION_F64 or CJ_PRECISION_F32_REFINE");
     const bool mixed = o.precision == CJ_PRECISION_F32_REFINE;
-    const int elem = mixed ? 4 : 8;
+    if (o.inner_precision != CJ_INNER_AUTO && o.inner_precision != CJ_INNER_F32 &&
+        o.inner_precision != CJ_INNER_F64)
+        return fail(CJ_ERR_ARG, "inner_precision must be CJ_INNER_AUTO, CJ_INNER_F32 or CJ_INNER_F64");
+    if (!mixed && o.inner_precision != CJ_INNER_AUTO)
+        return fail(CJ_ERR_ARG, "inner_precision applies to CJ_PRECISION_F32_REFINE plans only");
+    // Inner cycles of a refinement plan: FP32 unless forced to FP64 or, when
+    // automatic, eps32 * kappa_max / kappa_min exceeds kInnerF64Above (the
+    // FP32 cycle then solves the correction equation to little better than
+    // its own rounding: at 16384^2, 9-point, the product is 8.6 and FP32
+    // outer steps contract by about 0.45 each, stagnating at 4.2e-10, where
+    // FP64 cycles meet 1e-10 in the same time; at 8192^2, 2.2, FP32 cycles
+    // still reach 1e-10 in 20% less time than FP64 ones).
+    bool inner_f64 = false;
+    if (mixed) {
+        // the bounds do not depend on the tolerance or the cycle length
+        cj::Schedule probe;
+        std::string perr;
+        if (!cj::make_schedule(stencil, nx, ny, 0.5, o.h, 1, &probe, &perr)) return fail(CJ_ERR_ARG, perr);
+        const double eps32 = 1.1920928955078125e-07;   // 2^-23
+        inner_f64 = o.inner_precision == CJ_INNER_F64 ||
+                    (o.inner_precision == CJ_INNER_AUTO && eps32 * probe.kmax / probe.kmin > kInnerF64Above);
+    }
+    const int elem = (mixed && !inner_f64) ? 4 : 8;
     if (o.sweeps_per_launch > 1 && !cj::sweepk_supported(stencil, o.sweeps_per_launch, elem))
         return fail(CJ_ERR_ARG, "sweeps_per_launch not available for this stencil and precision "
                                 "(FP64: 5/9-point 1, 2, 3, 4, 6, 8, 10, 17-point 1, 2, 3, 4; "
@@ -692,7 +727,11 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol, const cj_o
         delete p;
         return fail(CJ_ERR_ARG, err);
     }
-    if (mixed) {
+    if (inner_f64) {
+        // FP64 inner cycles: the plan's FP64 schedule is the inner one (its
+        // cycle length is inner_M when given)
+        p->s = p->sin;
+    } else if (mixed) {
         // inner weight table: cycles of length sin.M, sin.M / 2, ..., 1
         p->w32_all.assign(2 * (size_t)p->sin.M, 0.0f);
         for (int m = p->sin.M; m >= 1; m /= 2) {
@@ -706,6 +745,7 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol, const cj_o
     }
     p->opt = o;
     p->precision = o.precision;
+    p->inner_f64 = inner_f64;
     p->max_cycles = o.max_cycles > 0 ? o.max_cycles : (mixed ? 50 : p->s.cycles_pred + 4);
     const int R = radius(stencil);
     const int frame = bc == CJ_BC_DIRICHLET_FRAME ? R : 0;
@@ -715,7 +755,7 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol, const cj_o
     // 5-point 56.5, K = 8: 58.7), K = 8 on smaller ones, where a cycle of whole
     // K-launches replays as one graph; 17-point K = 4 (132.3; K = 5 no longer
     // fits two waves per SIMD).  FP32: K = 8, 17-point K = 4.
-    if (mixed) {
+    if (mixed && !inner_f64) {
         // the corrections have zero boundary data in the same frame geometry
         p->L32 = cj::make_layout(nx, ny, 4, frame);
         p->K = 1;
@@ -734,7 +774,7 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol, const cj_o
     // fit per CU and on the grid; at 2048^2 the static rule's 16-row tiles spend
     // more row steps filling the level pipeline than producing), from a cost
     // model on smaller ones
-    p->tune_rows = o.tile_rows == 0 && (mixed ? p->K32 : p->K) > 1;
+    p->tune_rows = o.tile_rows == 0 && (p->f32_inner() ? p->K32 : p->K) > 1;
     if (o.graph < -1 || o.graph > 1) {
         delete p;
         return fail(CJ_ERR_ARG, "graph must be -1, 0 or 1");
@@ -756,7 +796,7 @@ cj_status cj_plan(int nx, int ny, int stencil, int bc, double tol, cj_plan_t* ou
 cj_status cj_plan_info(cj_plan_t p, double* kmin, double* kmax, int* M, int* cycles_pred,
                        const double** weights_host, size_t* workspace_bytes) {
     if (!p) return fail(CJ_ERR_ARG, "plan is NULL");
-    const cj::Schedule& s = p->mixed() ? p->sin : p->s;
+    const cj::Schedule& s = p->f32_inner() ? p->sin : p->s;
     if (kmin) *kmin = s.kmin;
     if (kmax) *kmax = s.kmax;
     if (M) *M = s.M;
@@ -768,8 +808,8 @@ cj_status cj_plan_info(cj_plan_t p, double* kmin, double* kmax, int* M, int* cyc
 
 cj_status cj_plan_launch_info(cj_plan_t p, int* sweeps_per_launch, int* tile_rows, int* workgroups) {
     if (!p) return fail(CJ_ERR_ARG, "plan is NULL");
-    const int K = p->mixed() ? p->K32 : p->K;
-    const cj::Tiles& T = K > 1 ? (p->mixed() ? p->TK32 : p->TK) : p->T;
+    const int K = p->f32_inner() ? p->K32 : p->K;
+    const cj::Tiles& T = K > 1 ? (p->f32_inner() ? p->TK32 : p->TK) : p->T;
     if (sweeps_per_launch) *sweeps_per_launch = K;
     if (tile_rows) *tile_rows = T.rows;
     if (workgroups) *workgroups = T.count();
@@ -801,7 +841,7 @@ cj_status cj_sweeps(cj_plan_t p, const double* f, double* u, long long n_sweeps,
     double g2 = 0.0;
     if ((st = stage_in(p, f, u, stream, &g2)) != CJ_OK) return st;
     double* answer = p->A;
-    if (p->mixed()) {
+    if (p->f32_inner()) {
         // the plan's working precision: u and g rounded to FP32, FP32 sweeps
         // (both iterates carry the boundary: B's ring equals A's)
         CJ_HIP(cj::launch_to_f32(p->L, p->L32, p->A, p->D1, stream));

@@ -169,3 +169,38 @@ def test_default_blocking_depth():
     for st, big, small in ((5, 10, 8), (9, 10, 8), (17, 4, 4)):
         assert cj.plan(4096, 1025, st, 1e-8).sweeps_per_launch == big
         assert cj.plan(2048, 2048, st, 1e-8).sweeps_per_launch == small
+
+
+def test_refinement_inner_precision_on_the_host():
+    """Refinement plans take FP64 inner cycles where eps32 * kmax / kmin > 4
+    (16384^2, 9-point: 8.6) and FP32 ones below (8192^2: 2.2); either can be
+    forced.  FP64 inner cycles report the FP64 schedule and blocking depth."""
+    eps32 = 2.0 ** -23
+    big = cj.plan(16384, 16384, 9, 1e-10, precision=cj.F32_REFINE)
+    o = cjm.plan(16384, 16384, 9, 1e-10)
+    assert eps32 * o.kmax / o.kmin > 4
+    assert (big.M, big.cycles_pred) == (o.M, o.cycles_pred)
+    assert big.sweeps_per_launch == 10                      # the FP64 default above 2^22 points
+    mid = cj.plan(8192, 8192, 9, 1e-10, precision=cj.F32_REFINE)
+    assert mid.sweeps_per_launch == 8                       # FP32 inner cycles
+    forced = cj.plan(8192, 8192, 9, 1e-10, precision=cj.F32_REFINE, inner_precision=cj.INNER_F64)
+    assert forced.sweeps_per_launch == 10 and forced.M == cjm.plan(8192, 8192, 9, 1e-10).M
+    f32 = cj.plan(16384, 16384, 9, 1e-10, precision=cj.F32_REFINE, inner_precision=cj.INNER_F32)
+    assert f32.sweeps_per_launch == 8
+    # FP64 inner cycles hold three more padded FP64 arrays instead of three FP32 ones
+    assert forced.workspace_bytes > mid.workspace_bytes
+    small = cj.plan(40, 30, 9, 1e-8, precision=cj.F32_REFINE, inner_precision=cj.INNER_F64, inner_M=64)
+    assert small.M == 64
+    for kw in ({"inner_precision": 3}, {"inner_precision": -1}, {"inner_precision": cj.INNER_F64, "precision": cj.F64}):
+        with pytest.raises(cj.CJError) as e:
+            cj.plan(40, 30, 9, 1e-8, **kw)
+        assert e.value.code == cj.CJ_ERR_ARG
+    # batches and servers run FP32 inner cycles only
+    L = cj.lib()
+    opt = cj.Options()
+    L.cj_options_init(ctypes.byref(opt))
+    opt.precision, opt.inner_precision = cj.F32_REFINE, cj.INNER_F64
+    h = ctypes.c_void_p()
+    code = L.cj_batch_create(1, (ctypes.c_int * 1)(10), (ctypes.c_int * 1)(10), (ctypes.c_int * 1)(9),
+                             (ctypes.c_double * 1)(1e-8), ctypes.byref(opt), ctypes.byref(h))
+    assert code == cj.CJ_ERR_ARG and not h.value

@@ -232,3 +232,31 @@ def test_c3_refinement_at_full_size(torch_cuda, nx, ny):
     assert abs(rr - r2["rel_residual"]) <= 1e-3 * rr + _residual_noise(st, f, got, nx, ny)
     assert rr <= 5e-10
     assert err2 <= 1e-8
+
+
+def test_c3_16384_refinement_takes_fp64_inner_cycles(torch_cuda):
+    """16384^2, 9-point, tol 1e-10: eps32 * kmax / kmin = 8.6, where FP32 inner
+    cycles stagnate near 4e-10; the refinement plan takes FP64 inner cycles by
+    itself, and its double-double iterate meets the tolerance by the oracle's
+    extended-precision residual."""
+    torch = torch_cuda
+    n, st, tol = 16384, 9, 1e-10
+    _say("case: C3 16384^2")
+    f = inputs.gaussian_bumps_rhs(n, n, seed=1705 + st)
+    p = cj.plan(n, n, st, tol, precision=cj.F32_REFINE)
+    q = cj.plan(n, n, st, tol)
+    assert (p.M, p.sweeps_per_launch) == (q.M, q.sweeps_per_launch)   # the FP64 schedule and kernel
+    q.destroy()
+    fd = _dev(torch, f)
+    u = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+    lo = torch.zeros_like(u)
+    r = cj.solve_dd(p, fd, u, lo)
+    hi, lo_h = _host(u), _host(lo)
+    del u, lo, fd
+    p.destroy()
+    ext = cjm.relative_residual_ext(st, f, hi, lo_h, n, n)
+    _say("double-double, FP64 inner cycles: status %s outer %d sweeps %d %.1f s relres %.3e oracle (extended) %.3e"
+         % (r["status"], r["cycles"], r["sweeps"], r["seconds"], r["rel_residual"], ext))
+    assert r["status"] == "ok" and r["rel_residual"] <= tol
+    assert ext <= 1.5 * tol
+    assert np.all(np.abs(lo_h) <= np.spacing(np.abs(hi)) / 2)

@@ -269,3 +269,45 @@ def test_double_double_not_converged_returns_the_last_iterate(torch_cuda, precis
           % (precision, r["status"], r["cycles"], r["rel_residual"], ext), flush=True)
     assert r["status"] == "not_converged" and r["cycles"] == 1
     assert abs(ext - r["rel_residual"]) <= 1e-6 * ext + 1e-15
+
+
+@pytest.mark.parametrize("st", [5, 9, 17])
+@pytest.mark.parametrize("frame", [False, True])
+def test_refinement_with_fp64_inner_cycles(torch_cuda, st, frame):
+    """A refinement plan with FP64 inner cycles (forced here; chosen
+    automatically where eps32 * kmax / kmin > 4): its sweeps are the FP64
+    plan's bits, cj_solve meets the tolerance by the oracle's residual and
+    agrees with the FP64 oracle's solution, and cj_solve_dd meets a tolerance
+    below the FP64 floor by the oracle's extended-precision residual."""
+    torch = torch_cuda
+    nx, ny = 211, 143
+    f = inputs.gaussian_bumps_rhs(nx, ny, seed=300 + st)
+    fd = _dev(torch, f)
+    bc = cj.BC_FRAME if frame else cj.BC_ZERO
+    obc = cjm.BC_FRAME if frame else cjm.BC_ZERO
+    u0 = inputs.expxy_frame(nx, ny, inputs.frame_width(st)) if frame else np.zeros((ny, nx))
+    p = cj.plan(nx, ny, st, 1e-10, precision=cj.F32_REFINE, inner_precision=cj.INNER_F64, bc=bc)
+    q = cj.plan(nx, ny, st, 1e-10, bc=bc)
+    assert (p.M, p.sweeps_per_launch) == (q.M, q.sweeps_per_launch)
+    a, b = _dev(torch, u0), _dev(torch, u0)
+    cj.sweeps(p, fd, a, 23)
+    cj.sweeps(q, fd, b, 23)
+    assert torch.equal(a, b)
+    u = _dev(torch, u0)
+    r = cj.solve(p, fd, u)
+    got = _host(u)
+    rr = cjm.relative_residual(st, f, got, nx, ny, bc=obc)
+    ref = cjm.solve(f, nx, ny, st, 1e-10, u0=u0 if frame else None, bc=obc)
+    err = _rel(got, ref["u"])
+    print("st %d frame %d: status %s, outer %d, sweeps %d, relres %.3e (oracle %.3e), err vs FP64 oracle %.3e"
+          % (st, frame, r["status"], r["cycles"], r["sweeps"], r["rel_residual"], rr, err), flush=True)
+    assert r["status"] == "ok" and rr <= 1e-10 * 1.01
+    assert err <= 50 * 1e-10
+    pd = cj.plan(nx, ny, st, 1e-14, precision=cj.F32_REFINE, inner_precision=cj.INNER_F64, bc=bc, max_cycles=30)
+    u = _dev(torch, u0)
+    lo = torch.zeros_like(u)
+    r = cj.solve_dd(pd, fd, u, lo)
+    ext = cjm.relative_residual_ext(st, f, _host(u), _host(lo), nx, ny, bc=obc)
+    print("  double-double: status %s, outer %d, relres %.3e, oracle (extended) %.3e"
+          % (r["status"], r["cycles"], r["rel_residual"], ext), flush=True)
+    assert r["status"] == "ok" and ext <= 1.5e-14
