@@ -231,6 +231,22 @@ cj_status cj_sweeps(cj_plan_t p, const double* f, double* u, long long n_sweeps,
 cj_status cj_residual(cj_plan_t p, const double* f, const double* u, void* stream,
                       double* rel_residual);
 
+/* Allocation-free form of cj_residual, for callers that cannot allocate
+ * device memory or wait on the host: code under HIP graph capture, serving
+ * loops that must not call hipMalloc.  The value is cj_residual's, from the
+ * same partial sums in the same order, but read straight from the caller's f
+ * and u (no staging copy, no plan workspace) and written to the DEVICE
+ * address rel_residual (one double) on `stream`; the call returns once the
+ * work is enqueued.  A NaN or Inf in f or u gives a non-finite value (there is
+ * no status for it).  It allocates nothing: the per-tile partial sums live in
+ * a fixed scratch array in the library, one per device (1 MiB, held until the
+ * process ends), which limits the grid to at most 65536 tiles of the plan's
+ * residual geometry (256 columns by 16 rows on large grids, e.g. 16384^2);
+ * larger grids give CJ_ERR_ARG.  Calls that overlap on one device share that
+ * array and race: order them on one stream.  The plan is only read (it need
+ * not have a workspace, and is not bound to the device). */
+cj_status cj_residual_noalloc(cj_plan_t p, const double* f, const double* u, double* rel_residual, void* stream);
+
 /* au = A u = -Delta_h u (the stencil apply) on the interior; au has the
  * nx*ny layout of f.  With CJ_BC_DIRICHLET_FRAME the frame values enter the
  * stencil as they stand. */

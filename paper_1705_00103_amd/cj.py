@@ -46,7 +46,7 @@ STATUS_NAMES = {
 
 # Function names declared in include/cj.h (checked against the header by the tests).
 EXPORTS = ("cj_options_init", "cj_plan", "cj_plan_ex", "cj_plan_info", "cj_plan_launch_info", "cj_solve",
-           "cj_solve_dd", "cj_sweeps", "cj_residual", "cj_apply", "cj_plan_destroy",
+           "cj_solve_dd", "cj_sweeps", "cj_residual", "cj_residual_noalloc", "cj_apply", "cj_plan_destroy",
            "cj_status_string", "cj_last_error",
            "cj_batch_create", "cj_batch_info", "cj_batch_solve", "cj_batch_destroy",
            "cj_server_create", "cj_server_submit", "cj_server_step", "cj_server_stats", "cj_server_destroy")
@@ -120,6 +120,8 @@ def lib():
         L.cj_sweeps.restype = c_int
         L.cj_residual.argtypes = [vp, vp, vp, vp, dp]
         L.cj_residual.restype = c_int
+        L.cj_residual_noalloc.argtypes = [vp, vp, vp, vp, vp]
+        L.cj_residual_noalloc.restype = c_int
         L.cj_apply.argtypes = [vp, vp, vp, vp]
         L.cj_apply.restype = c_int
         L.cj_plan_destroy.argtypes = [vp]
@@ -283,6 +285,18 @@ def residual(p, f, u, stream=None):
     _check(lib().cj_residual(p.handle, _grid_ptr(f, p, "f"), _grid_ptr(u, p, "u", True), _stream(stream),
                              ctypes.byref(out)), "cj_residual")
     return out.value
+
+
+def residual_noalloc(p, f, u, out, stream=None):
+    """cj_residual_noalloc: ||f - A u|| / ||f|| written to out (a float64 GPU
+    tensor with one element) on the stream, without waiting and without any
+    device allocation."""
+    import torch
+    if not isinstance(out, torch.Tensor) or out.device.type != "cuda" or out.dtype != torch.float64 \
+            or out.numel() < 1:
+        raise ValueError("out must be a float64 GPU tensor")
+    _check(lib().cj_residual_noalloc(p.handle, _grid_ptr(f, p, "f"), _grid_ptr(u, p, "u", True),
+                                     ctypes.c_void_p(out.data_ptr()), _stream(stream)), "cj_residual_noalloc")
 
 
 def apply(p, u, au, stream=None):

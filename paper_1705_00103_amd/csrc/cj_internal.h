@@ -174,6 +174,15 @@ hipError_t launch_segmented_reduce(const double* part, const int* seg, int n_seg
 // out[0] <- sum of part[0 .. n) in a fixed order (one workgroup).
 hipError_t launch_reduce(const double* part, int n, double* out, hipStream_t stream);
 
+// Allocation-free relative residual (cj_residual_noalloc): out[0] (device)
+// <- ||f - A u|| / ||f|| (frame: over the lifted right-hand side) read from
+// the caller's f and u, with the per-tile partial sums in the library's
+// static per-device scratch array; T the plan's single-sweep tiles, at most
+// kNoallocMaxTiles of them (else hipErrorInvalidValue).
+constexpr int kNoallocMaxTiles = 65536;
+hipError_t launch_residual_noalloc(int stencil, int nx, int ny, bool frame, const Tiles& T, double scale,
+                                   const double* f, const double* u, double* out, hipStream_t stream);
+
 // au (user layout) <- dscale * (u - sum c_hat u_nbr) = A u, with dscale = D.
 hipError_t launch_apply(int stencil, const Layout& L, const double* A, double dscale,
                         double* au, hipStream_t stream);

@@ -20,6 +20,8 @@
 // produces the same bits.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "cj_internal.h"
 
 namespace cj {
@@ -908,6 +910,112 @@ __global__ __launch_bounds__(256) void apply_kernel(const double* __restrict__ A
     au[(size_t)(y - 1) * (size_t)nx + (size_t)(x - 1)] = dscale * (v[R][R] - neighbour_sum<double, ST>(v));
 }
 
+// ------------------------------------------------------------ allocation-free residual
+// The relative residual of cj_residual read straight from the caller's arrays,
+// with no staging copy: window values come from u itself (homogeneous data:
+// zero on the Dirichlet ring and the odd reflection beyond it; boundary data:
+// the frame array), g = scale * f is formed as stage-in forms it, and the
+// per-tile partial sums follow the same tiles, rows and orders as the staged
+// path (r^2 as the residual kernel sums it; the denominator as stage-in sums
+// g^2 or, with a frame, as the residual kernel sums the residual of the zero
+// interior), so both paths reduce the same partial sums in the same order.
+
+// Value at node (x, y), -R <= x - 1, of the caller's u: fg = 0, the nx x ny
+// interior with the homogeneous ring (zero at 0 and n + 1, odd reflection at
+// -1 and n + 2); fg > 0, the (nx + 2 fg) x (ny + 2 fg) frame array, with the
+// interior read as zero when zero_interior is set.
+__device__ __forceinline__ double user_node(const double* __restrict__ u, int nx, int ny, int fg, int x, int y,
+                                            bool zero_interior) {
+    if (fg > 0) {
+        if (zero_interior && x >= 1 && x <= nx && y >= 1 && y <= ny) return 0.0;
+        return u[(size_t)(y - 1 + fg) * ((size_t)nx + 2 * (size_t)fg) + (size_t)(x - 1 + fg)];
+    }
+    double sgn = 1.0;
+    if (x < 0) { x = -x; sgn = -sgn; }
+    if (x > nx + 1) { x = 2 * (nx + 1) - x; sgn = -sgn; }
+    if (y < 0) { y = -y; sgn = -sgn; }
+    if (y > ny + 1) { y = 2 * (ny + 1) - y; sgn = -sgn; }
+    if (x < 1 || x > nx || y < 1 || y > ny) return 0.0;
+    return sgn * u[(size_t)(y - 1) * (size_t)nx + (size_t)(x - 1)];
+}
+
+template <int ST, bool FRAME>
+__global__ __launch_bounds__(256) void residual_noalloc_kernel(const double* __restrict__ f,
+                                                               const double* __restrict__ u, double scale, int nx,
+                                                               int ny, int tiles_x, int rows,
+                                                               double* __restrict__ part_r,
+                                                               double* __restrict__ part_d) {
+    constexpr int R = Stencil<ST>::R;
+    constexpr int W = 2 * R + 1;
+    constexpr int FG = FRAME ? R : 0;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tx = tile % tiles_x, ty = tile / tiles_x;
+    const int x = tx * (int)blockDim.x + (int)threadIdx.x + 1;
+    const bool active = x <= nx;
+    const int xl = active ? x : nx;   // idle lanes read a valid column; their sums are dropped
+    const int y0 = ty * rows + 1;
+    const int y1 = min(y0 + rows, ny + 1);
+    double v[W][W], v0[FRAME ? W : 1][W];
+#pragma unroll
+    for (int r = 1; r < W; ++r)
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+            v[r][c] = user_node(u, nx, ny, FG, xl - R + c, y0 - R + r - 1, false);
+            if (FRAME) v0[r][c] = user_node(u, nx, ny, FG, xl - R + c, y0 - R + r - 1, true);
+        }
+    double acc = 0.0, accd = 0.0;
+    for (int y = y0; y < y1; ++y) {
+#pragma unroll
+        for (int r = 0; r < W - 1; ++r)
+#pragma unroll
+            for (int c = 0; c < W; ++c) {
+                v[r][c] = v[r + 1][c];
+                if (FRAME) v0[r][c] = v0[r + 1][c];
+            }
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+            v[W - 1][c] = user_node(u, nx, ny, FG, xl - R + c, y + R, false);
+            if (FRAME) v0[W - 1][c] = user_node(u, nx, ny, FG, xl - R + c, y + R, true);
+        }
+        const double gv = scale * f[(size_t)(y - 1) * (size_t)nx + (size_t)(xl - 1)];
+        const double res = window_residual<double, ST>(v, gv);
+        acc = fmat<double>(res, res, acc);
+        if constexpr (FRAME) {
+            const double res0 = window_residual<double, ST>(v0, gv);
+            accd = fmat<double>(res0, res0, accd);
+        } else {
+            accd = fmat<double>(gv, gv, accd);
+        }
+    }
+    if (!active) {
+        acc = 0.0;
+        accd = 0.0;
+    }
+    const double tr = block_sum(acc);
+    __syncthreads();   // thread 0 has read block_sum's shared slots before they are reused
+    const double td = block_sum(accd);
+    if (threadIdx.x == 0) {
+        part_r[tile] = tr;
+        part_d[tile] = td;
+    }
+}
+
+// out[0] <- sqrt(sum part_r) / sqrt(sum part_d) (0 when the second sum is 0),
+// each sum in reduce_kernel's order.
+__global__ __launch_bounds__(256) void ratio_kernel(const double* __restrict__ part_r,
+                                                    const double* __restrict__ part_d, int n,
+                                                    double* __restrict__ out) {
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        a += part_r[k];
+        b += part_d[k];
+    }
+    const double r2 = block_sum(a);
+    __syncthreads();
+    const double d2 = block_sum(b);
+    if (threadIdx.x == 0) out[0] = d2 == 0.0 ? 0.0 : __builtin_sqrt(r2) / __builtin_sqrt(d2);
+}
+
 // The 17-point stencil has two kernel families: REFL for homogeneous data
 // (reflected outer ring) and one for boundary data in a frame (L.frame > 0).
 // The 5- and 9-point kernels read only the Dirichlet ring, which is data in
@@ -1271,6 +1379,67 @@ Tiles make_tiles(int nx, int ny, int rows_request) {
     T.rows = rows;
     T.tiles_y = (ny + rows - 1) / rows;
     return T;
+}
+
+}  // namespace cj
+
+// Scratch of cj_residual_noalloc: the per-tile partial sums of the residual
+// (first kNoallocMaxTiles doubles) and of the denominator (the next ones).
+// Every device the library runs on holds its own copy until the process ends;
+// host code reaches it only through the address hipGetSymbolAddress gives on
+// that device.
+static __device__ __align__(256) double scratch[2 * cj::kNoallocMaxTiles];
+
+namespace cj {
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(double** out) {
+    *out = nullptr;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch[dev];
+    return hipSuccess;
+}
+
+hipError_t launch_residual_noalloc(int stencil, int nx, int ny, bool frame, const Tiles& T, double scale,
+                                   const double* f, const double* u, double* out, hipStream_t stream) {
+    if (T.count() > kNoallocMaxTiles || T.count() < 1) return hipErrorInvalidValue;
+    double* s = nullptr;
+    const hipError_t e = noalloc_scratch(&s);
+    if (e != hipSuccess) return e;
+    double* pr = s;
+    double* pd = s + kNoallocMaxTiles;
+    const dim3 grid(T.count()), block(T.width);
+#define CJ_NA_CASE(ST)                                                                                         \
+    if (frame)                                                                                                 \
+        hipLaunchKernelGGL((residual_noalloc_kernel<ST, true>), grid, block, 0, stream, f, u, scale, nx, ny,  \
+                           T.tiles_x, T.rows, pr, pd);                                                         \
+    else                                                                                                       \
+        hipLaunchKernelGGL((residual_noalloc_kernel<ST, false>), grid, block, 0, stream, f, u, scale, nx, ny, \
+                           T.tiles_x, T.rows, pr, pd);
+    switch (stencil) {
+    case 5: CJ_NA_CASE(5) break;
+    case 9: CJ_NA_CASE(9) break;
+    case 17: CJ_NA_CASE(17) break;
+    default: return hipErrorInvalidValue;
+    }
+#undef CJ_NA_CASE
+    hipLaunchKernelGGL(ratio_kernel, dim3(1), dim3(256), 0, stream, pr, pd, T.count(), out);
+    return hipGetLastError();
 }
 
 }  // namespace cj

@@ -879,6 +879,24 @@ cj_status cj_residual(cj_plan_t p, const double* f, const double* u, void* strea
     return CJ_OK;
 }
 
+cj_status cj_residual_noalloc(cj_plan_t p, const double* f, const double* u, double* rel_residual,
+                              void* stream_) {
+    if (!p) return fail(CJ_ERR_ARG, "plan is NULL");
+    cj_status st;
+    if ((st = check_ptr(f, "f")) != CJ_OK || (st = check_ptr(u, "u")) != CJ_OK ||
+        (st = check_ptr(rel_residual, "rel_residual")) != CJ_OK)
+        return st;
+    if (p->T.count() > cj::kNoallocMaxTiles)
+        return fail(CJ_ERR_ARG, "the grid has " + std::to_string(p->T.count()) +
+                                    " residual tiles; cj_residual_noalloc holds partial sums for at most " +
+                                    std::to_string(cj::kNoallocMaxTiles));
+    const double scale = p->s.h * p->s.h / centre_over_s(p->s.stencil);   // D^{-1}, as stage-in applies it
+    const hipError_t e = cj::launch_residual_noalloc(p->s.stencil, p->s.nx, p->s.ny, p->L.frame > 0, p->T, scale, f,
+                                                     u, rel_residual, static_cast<hipStream_t>(stream_));
+    if (e != hipSuccess) return fail(CJ_ERR_HIP, std::string("cj_residual_noalloc: ") + hipGetErrorString(e));
+    return CJ_OK;
+}
+
 cj_status cj_apply(cj_plan_t p, const double* u, double* au, void* stream_) {
     if (!p) return fail(CJ_ERR_ARG, "plan is NULL");
     cj_status st;
