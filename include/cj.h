@@ -270,19 +270,29 @@ typedef struct {
     long long points;          /* sum of nx*ny */
     double    updates;         /* sum of nx*ny*sweeps (FP32 grid-point updates) */
     double    seconds;         /* host wall time of cj_batch_solve */
-    int       reserved[8];
+    int       sweeps_per_launch[3];   /* blocked depth K the 5-, 9- and 17-point problems ran at
+                                         (0: no such problem) */
+    int       tile_rows[3];           /* and their tile height (chosen by the autotuner when
+                                         sweeps_per_launch and tile_rows are automatic) */
+    int       reserved[2];
 } cj_batch_stats;
 
 /* n problems; nx, ny, stencil, tol are arrays of length n (read during the
  * call only).  opt: precision must be CJ_PRECISION_F32_REFINE; M, inner_M and
- * h must be 0; sweeps_per_launch 0 (automatic: 8, 17-point 4), 2, 4 or 8;
- * tile_rows and max_cycles (outer steps per problem, 0 = 50) apply to all.
- * Host only; the device workspace is allocated by the first solve. */
+ * h must be 0; sweeps_per_launch 0 (automatic), 2, 4 or 8 (17-point at most
+ * 4); tile_rows and max_cycles (outer steps per problem, 0 = 50) apply to
+ * all.  With sweeps_per_launch and
+ * tile_rows both automatic, the first solve times every (K in {8, 4, 2},
+ * tile rows in {16, 32, 64, 128}) per stencil group on the problems
+ * themselves before their first inner cycle and keeps the fastest per sweep
+ * (results do not depend on it); cj_batch_info and cj_batch_stats report the
+ * choice.  Host only; the device workspace is allocated by the first solve. */
 cj_status cj_batch_create(int n, const int* nx, const int* ny, const int* stencil, const double* tol,
                           const cj_options* opt, cj_batch_t* out);
 
-/* Problem i's longest inner cycle M, its sweeps per launch, and the batch's
- * device workspace in bytes.  Any output pointer may be NULL. */
+/* Problem i's longest inner cycle M, its sweeps per launch (after the first
+ * solve: the autotuner's choice), and the batch's device workspace in bytes.
+ * Any output pointer may be NULL. */
 cj_status cj_batch_info(cj_batch_t b, int i, int* M, int* sweeps_per_launch, size_t* workspace_bytes);
 
 /* Solves all problems: f[i], u[i] are device pointers laid out as in

@@ -75,11 +75,14 @@ class Result(ctypes.Structure):
 
 class BatchStats(ctypes.Structure):
     _fields_ = [("supersteps", ctypes.c_int), ("launches", ctypes.c_longlong), ("points", ctypes.c_longlong),
-                ("updates", ctypes.c_double), ("seconds", ctypes.c_double), ("reserved", ctypes.c_int * 8)]
+                ("updates", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("sweeps_per_launch", ctypes.c_int * 3), ("tile_rows", ctypes.c_int * 3),
+                ("reserved", ctypes.c_int * 2)]
 
     def as_dict(self):
         return dict(supersteps=self.supersteps, launches=self.launches, points=self.points, updates=self.updates,
-                    seconds=self.seconds)
+                    seconds=self.seconds, sweeps_per_launch=dict(zip((5, 9, 17), self.sweeps_per_launch)),
+                    tile_rows=dict(zip((5, 9, 17), self.tile_rows)))
 
 
 class CJError(RuntimeError):

@@ -224,6 +224,13 @@ public:
     DevBuf<double> norm;
     double* part = nullptr;
     size_t part_cap = 0;
+    // Autotuner of a batch (all problems known up front, depth and tile height
+    // automatic): before the first inner cycle it times (K, tile rows) per
+    // stencil group on the problems themselves and keeps the fastest per sweep.
+    bool autotune = false;
+    bool tuned = false;
+    int tuned_K[3] = {0, 0, 0};
+    int tuned_rows[3] = {0, 0, 0};
     int step_no = 0;
     // Most super-steps one engine step enqueues (0: no limit).  A step runs up
     // to the first inner-cycle end among the active problems, where the host
@@ -398,6 +405,115 @@ public:
         return false;
     }
 
+    static int group_of(int stencil) { return stencil == 5 ? 0 : stencil == 9 ? 1 : 2; }
+
+    void set_rows(Problem* p, int rows) {
+        p->TK = cj::make_tiles_k(p->nx, p->ny, p->K, p->stencil == 17 ? 2 : 1, rows);
+        desc(p).strips_x = p->TK.tiles_x;
+        desc(p).rows_k = p->TK.rows;
+    }
+
+    // A new blocked depth for a problem at the start of a cycle (its cycle
+    // lengths, at least 16, are multiples of every depth used here).
+    void set_depth(Problem* p, int K) {
+        p->K = K;
+        set_rows(p, p->TK.rows);
+    }
+
+    // Work list of the active problems' blocked tiles, grouped by stencil.
+    cj_status build_work(hipStream_t stream) {
+        size_t n = 0;
+        for (Problem* p : live)
+            if (p->state == State::Active) n += p->TK.count();
+        if (work.cap < n) {
+            CJB_HIP(hipStreamSynchronize(stream));
+            if (work.ensure(n) != hipSuccess) return bfail(CJ_ERR_NOMEM, "work list allocation");
+        }
+        size_t pos = 0;
+        for (int gi = 0; gi < 3; ++gi) {
+            const size_t start = pos;
+            for (Problem* p : live)
+                if (p->state == State::Active && p->stencil == kStencils[gi])
+                    for (int t = 0; t < p->TK.count(); ++t) work.h[pos++] = cj::BatchItem{p->slot, t};
+            group_size[gi] = pos - start;
+        }
+        CJB_HIP(hipMemcpyAsync(work.d, work.h, pos * sizeof(cj::BatchItem), hipMemcpyHostToDevice, stream));
+        CJB_HIP(hipStreamSynchronize(stream));
+        return CJ_OK;
+    }
+
+    // The batch autotuner.  Every active problem is at the start of its first
+    // inner cycle: its correction d1 is zero and d2 is free.  For each stencil
+    // group and each (K, tile rows) candidate it times two super-steps of the
+    // group's problems (two launches), which read d1, write d2, then d1, and
+    // scores the time per sweep; the fastest is kept
+    // for the rest of the batch's life (cj_batch_stats reports it).  d1 and d2
+    // are zeroed afterwards.  Tiles only partition the grids and a K-sweep
+    // launch gives the bits of K single sweeps, so the choice changes speed
+    // only.
+    cj_status tune(hipStream_t stream) {
+        static const int kK[3] = {8, 4, 2};
+        static const int kRows[4] = {16, 32, 64, 128};
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        CJB_HIP(hipEventCreate(&e0));
+        CJB_HIP(hipEventCreate(&e1));
+        cj_status st = CJ_OK;
+        for (int gi = 0; gi < 3 && st == CJ_OK; ++gi) {
+            std::vector<Problem*> grp;
+            for (Problem* p : live)
+                if (p->state == State::Active && p->stencil == kStencils[gi]) grp.push_back(p);
+            if (grp.empty()) continue;
+            float best = -1.0f;
+            int bestK = grp[0]->K, bestRows = grp[0]->TK.rows;
+            for (int K : kK) {
+                if (kStencils[gi] == 17 && K > 4) continue;
+                for (int rows : kRows) {
+                    for (Problem* p : grp) {
+                        p->K = K;
+                        set_rows(p, rows);
+                        desc(p).cycle_start = step_no;
+                    }
+                    if ((st = upload_probs(stream)) != CJ_OK) break;
+                    if ((st = build_work(stream)) != CJ_OK) break;
+                    size_t base = 0;
+                    for (int g = 0; g < gi; ++g) base += group_size[g];
+                    const int n_items = (int)group_size[gi];
+                    float ms = 0.0f;
+                    hipError_t e = hipEventRecord(e0, stream);
+                    for (int k = 0; k < 2 && e == hipSuccess; ++k)
+                        e = cj::launch_batch_sweepk(kStencils[gi], K, probs.d, work.d + base, n_items, step_no + k,
+                                                    stream);
+                    if (e == hipSuccess) e = hipEventRecord(e1, stream);
+                    if (e == hipSuccess) e = hipEventSynchronize(e1);
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                    if (e != hipSuccess) {
+                        st = bfail(CJ_ERR_HIP, std::string("batch autotuner: ") + hipGetErrorString(e));
+                        break;
+                    }
+                    const float per_sweep = ms / (2.0f * (float)K);
+                    if (best < 0.0f || per_sweep < best) {
+                        best = per_sweep;
+                        bestK = K;
+                        bestRows = rows;
+                    }
+                }
+                if (st != CJ_OK) break;
+            }
+            tuned_K[gi] = bestK;
+            tuned_rows[gi] = bestRows;
+            for (Problem* p : grp) {
+                char* base = pool + p->block;
+                if (st == CJ_OK && hipMemsetAsync(base + p->off_d1, 0, p->off_w - p->off_d1, stream) != hipSuccess)
+                    st = bfail(CJ_ERR_HIP, "batch autotuner: clearing the corrections");
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (st != CJ_OK) return st;
+        tuned = true;
+        return CJ_OK;
+    }
+
     // One engine step (see the file comment).  Finished problems are appended to *done.
     cj_status step(hipStream_t stream, std::vector<Problem*>* done) {
         cj_status st;
@@ -427,7 +543,19 @@ public:
         for (Problem* p : live) any_active = any_active || p->state == State::Active;
         if (any_active) {
             if (rebuild) {
-                if (opt.tile_rows == 0) {
+                bool all_fresh = true;   // every active problem is at the start of its first cycle
+                for (Problem* p : live)
+                    if (p->state == State::Active && (p->j != 0 || p->outer != 0)) all_fresh = false;
+                if (autotune && !tuned && all_fresh && (st = tune(stream)) != CJ_OK) return st;
+                if (autotune && tuned) {
+                    for (Problem* p : live)
+                        if (p->state == State::Active) {
+                            const int gi = group_of(p->stencil);
+                            if (p->j == 0 && p->K != tuned_K[gi]) set_depth(p, tuned_K[gi]);
+                            if (p->TK.rows != std::min(tuned_rows[gi], p->ny)) set_rows(p, tuned_rows[gi]);
+                        }
+                    if ((st = upload_probs(stream)) != CJ_OK) return st;
+                } else if (opt.tile_rows == 0) {
                     // Tile height from the load: 64 rows while the active problems
                     // have at least 2048 tiles (the device is full and taller tiles
                     // waste less on their pipeline fill), shorter (down to 16) when
@@ -469,23 +597,7 @@ public:
                         }
                     if ((st = upload_probs(stream)) != CJ_OK) return st;
                 }
-                size_t n = 0;
-                for (Problem* p : live)
-                    if (p->state == State::Active) n += p->TK.count();
-                if (work.cap < n) {
-                    CJB_HIP(hipStreamSynchronize(stream));
-                    if (work.ensure(n) != hipSuccess) return bfail(CJ_ERR_NOMEM, "work list allocation");
-                }
-                size_t pos = 0;
-                for (int gi = 0; gi < 3; ++gi) {
-                    const size_t start = pos;
-                    for (Problem* p : live)
-                        if (p->state == State::Active && p->stencil == kStencils[gi])
-                            for (int t = 0; t < p->TK.count(); ++t) work.h[pos++] = cj::BatchItem{p->slot, t};
-                    group_size[gi] = pos - start;
-                }
-                CJB_HIP(hipMemcpyAsync(work.d, work.h, pos * sizeof(cj::BatchItem), hipMemcpyHostToDevice, stream));
-                CJB_HIP(hipStreamSynchronize(stream));
+                if ((st = build_work(stream)) != CJ_OK) return st;
                 rebuild = false;
             }
             // super-steps until the first cycle end among the active problems
@@ -707,6 +819,7 @@ cj_status cj_batch_create(int n, const int* nx, const int* ny, const int* stenci
     cj_batch_s* b = new (std::nothrow) cj_batch_s();
     if (!b) return bfail(CJ_ERR_NOMEM, "host allocation");
     b->eng.opt = o;
+    b->eng.autotune = Kreq == 0 && o.tile_rows == 0;
     b->eng.Kreq = Kreq;
     b->eng.max_outer = o.max_cycles > 0 ? o.max_cycles : 50;
     b->P.resize(n);
@@ -793,6 +906,11 @@ cj_status cj_batch_solve(cj_batch_t b, const double* const* f, double* const* u,
         stats->points = pts;
         stats->updates = E.updates;
         stats->seconds = secs;
+        for (const Problem& p : b->P) {
+            const int gi = Engine::group_of(p.stencil);
+            stats->sweeps_per_launch[gi] = p.K;
+            stats->tile_rows[gi] = std::max(stats->tile_rows[gi], p.TK.rows);
+        }
     }
     return worst;
 }

@@ -81,3 +81,32 @@ def test_batch_of_many_uneven_problems(torch_cuda):
         if i % 6 == 0:
             rr = cjm.relative_residual(st, hf[i], us[i].cpu().numpy(), nx, ny)
             assert rr <= 1.01e-8
+
+
+def test_batch_at_the_c4_shape_range(torch_cuda):
+    """64 problems with nx, ny log-uniform over [64, 2048] (the batched
+    workload's range), 9-point, tol 1e-8: every result is bit-identical to the
+    single-problem refined solve of the same problem and meets its tolerance
+    by the oracle's residual."""
+    torch = torch_cuda
+    shapes = inputs.log_uniform_shapes(64, seed=1705, lo=64, hi=2048)
+    stencils = [9] * len(shapes)
+    tols = [1e-8] * len(shapes)
+    infos = []
+    hf, fs, us, res, stats = _run_batch(torch, shapes, stencils, tols, seed=2000, infos=infos)
+    print("batch stats", stats, "points", sum(nx * ny for nx, ny in shapes), flush=True)
+    worst = 0.0
+    for i, (nx, ny) in enumerate(shapes):
+        r = res[i]
+        assert r["status"] == "ok", (i, r)
+        p = cj.plan(nx, ny, 9, 1e-8, precision=cj.F32_REFINE, inner_M=infos[i]["M"],
+                    sweeps_per_launch=infos[i]["sweeps_per_launch"])
+        u1 = torch.zeros(ny, nx, dtype=torch.float64, device="cuda")
+        r1 = cj.solve(p, fs[i], u1)
+        p.destroy()
+        assert (r["cycles"], r["sweeps"]) == (r1["cycles"], r1["sweeps"])
+        assert torch.equal(us[i], u1)
+        rr = cjm.relative_residual(9, hf[i], us[i].cpu().numpy(), nx, ny)
+        worst = max(worst, rr)
+        assert rr <= 1.01e-8
+    print("largest oracle relres %.3e" % worst, flush=True)

@@ -89,3 +89,49 @@ def test_oversized_request_is_refused(torch_cuda):
         srv.submit(512, 512, 9, 1e-8, f, u)
     assert e.value.code == cj.CJ_ERR_NOMEM
     srv.destroy()
+
+
+def test_large_requests_are_the_same_alone_and_in_the_mix(torch_cuda):
+    """Requests up to 4096 x 2048 (the serving workload's upper range) among
+    small ones, with a budget that holds one large request and a few small ones
+    at a time: each result is the same bits as the request served alone and
+    meets its tolerance by the oracle's residual."""
+    torch = torch_cuda
+    shapes = [(3000, 2500), (96, 80), (4096, 2048), (300, 17), (129, 129), (2048, 2048), (64, 700), (33, 33)]
+    stencils = [9, 5, 5, 9, 9, 9, 5, 9]
+    tols = [1e-10, 1e-8, 1e-6, 1e-10, 1e-8, 1e-8, 1e-6, 1e-10]
+    n = len(shapes)
+    hf = [inputs.gaussian_bumps_rhs(nx, ny, seed=700 + i) for i, (nx, ny) in enumerate(shapes)]
+    fs = [torch.from_numpy(f).to("cuda") for f in hf]
+    us = [torch.zeros_like(f) for f in fs]
+    budget = 4096 * 2048 * 30 + (8 << 20)          # about one large request and a few small ones
+    srv = cj.Server(hbm_budget_bytes=budget)
+    tickets, results, steps = {}, {}, 0
+    pending = list(range(n))
+    while pending or len(results) < n:
+        if pending and steps % 2 == 0:
+            i = pending.pop(0)
+            nx, ny = shapes[i]
+            tickets[srv.submit(nx, ny, stencils[i], tols[i], fs[i], us[i])] = i
+        for tk, r in srv.step():
+            results[tickets[tk]] = r
+        steps += 1
+        assert steps < 200000
+    srv.destroy()
+    for i in range(n):
+        nx, ny = shapes[i]
+        got = us[i].cpu().numpy()
+        srv1 = cj.Server(hbm_budget_bytes=budget)
+        u = torch.zeros(ny, nx, dtype=torch.float64, device="cuda")
+        srv1.submit(nx, ny, stencils[i], tols[i], fs[i], u)
+        done = []
+        while not done:
+            done = srv1.step()
+        srv1.destroy()
+        ra, r = done[0][1], results[i]
+        rr = cjm.relative_residual(stencils[i], hf[i], got, nx, ny)
+        print(i, (nx, ny), stencils[i], tols[i], r["status"], r["cycles"], ra["cycles"], "%.3e" % rr, flush=True)
+        assert r["status"] == ra["status"] == "ok"
+        assert (r["cycles"], r["sweeps"]) == (ra["cycles"], ra["sweeps"])
+        assert np.array_equal(got, u.cpu().numpy())
+        assert rr <= tols[i] * 1.01
