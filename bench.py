@@ -48,7 +48,11 @@ METRIC = "grid-point updates/s + time-to-tol (1e-10 rel resid); p50/p99 solve la
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = 24.0   # FP64: u and g read, u' written
 KERNEL_SRC = os.path.join(ROOT, "paper_1705_00103_amd", "csrc", "kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweepk9_f64_8192_traffic.md")
+
+def traffic_file(n, stencil):
+    """The committed counter summary of the blocked FP64 sweep on an n x n grid."""
+    return os.path.join(ROOT, "profiles", "sweepk%d_f64_%d_traffic.md" % (stencil, n))
+
 
 
 def kernel_hash():
@@ -68,9 +72,10 @@ def measured_traffic(n, stencil, K, rows):
     holds no figure for this launch geometry (K, tile rows).  The summary gives
     the bench's own tile height (workload line) and other heights the tile tuner
     may pick (lines "traffic rows=R ...: bytes")."""
-    if not os.path.exists(TRAFFIC_FILE):
+    path = traffic_file(n, stencil)
+    if not os.path.exists(path):
         return None
-    text = open(TRAFFIC_FILE).read()
+    text = open(path).read()
     m = re.search(r"kernels\.hip sha256\[:16\][^:\n]*:\s*([0-9a-f]{16})", text)
     t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
     w = re.search(r"workload:\s*n=(\d+)\s+stencil=(\d+)\s+K=(\d+)\s+rows=(\d+)", text)

@@ -132,7 +132,15 @@ typedef struct {
     int    method;             /* cj_method; 0 = CJ_METHOD_CHEBYSHEV */
     int    inner_precision;    /* cj_inner_precision of a CJ_PRECISION_F32_REFINE plan; must be
                                   0 otherwise */
-    int    reserved[3];        /* must be zero */
+    int    single_workgroup;   /* FP64 5- and 9-point plans whose padded grid fits in one CU's LDS
+                                  (at most 1024 columns and 16 rows per lane of a 1024-lane
+                                  workgroup, e.g. 128^2): run the whole solve in one launch of one
+                                  workgroup holding the grid in LDS (the same iterates; the residual
+                                  is summed in another order); 0 = automatic (when it fits with
+                                  bands of at most 4 rows per lane, e.g. 64^2, the sizes where one
+                                  CU outpaces the launched cycles), 1 = required (CJ_ERR_ARG if it
+                                  does not fit), -1 = never */
+    int    reserved[2];        /* must be zero */
 } cj_options;
 
 /* Outcome of a solve. */

@@ -57,7 +57,7 @@ class Options(ctypes.Structure):
                 ("sweeps_per_launch", ctypes.c_int), ("tile_rows", ctypes.c_int),
                 ("h", ctypes.c_double), ("precision", ctypes.c_int), ("inner_M", ctypes.c_int),
                 ("graph", ctypes.c_int), ("method", ctypes.c_int), ("inner_precision", ctypes.c_int),
-                ("reserved", ctypes.c_int * 3)]
+                ("single_workgroup", ctypes.c_int), ("reserved", ctypes.c_int * 2)]
 
 
 class Result(ctypes.Structure):
@@ -175,13 +175,13 @@ class Plan:
 
     def __init__(self, nx, ny, stencil=9, tol=1e-10, M=0, max_cycles=0, sweeps_per_launch=0,
                  tile_rows=0, h=0.0, bc=BC_ZERO, precision=F64, inner_M=0, graph=0, method=CHEBYSHEV,
-                 inner_precision=INNER_AUTO):
+                 inner_precision=INNER_AUTO, single_workgroup=0):
         L = lib()
         o = Options()
         L.cj_options_init(ctypes.byref(o))
         o.M, o.max_cycles, o.sweeps_per_launch, o.tile_rows, o.h = M, max_cycles, sweeps_per_launch, tile_rows, h
         o.precision, o.inner_M, o.graph, o.method = precision, inner_M, graph, method
-        o.inner_precision = inner_precision
+        o.inner_precision, o.single_workgroup = inner_precision, single_workgroup
         self.precision, self.bc, self.method = precision, bc, method
         # width of u's boundary frame (CJ_BC_DIRICHLET_FRAME)
         self.frame = (2 if stencil == 17 else 1) if bc == BC_FRAME else 0

@@ -760,6 +760,7 @@ cj_status engine_options(const cj_options* opt, cj_options* o, int* Kreq) {
         return bfail(CJ_ERR_ARG, "batched and served solves run FP32 sweeps inside FP64 refinement: set precision "
                                  "= CJ_PRECISION_F32_REFINE");
     if (o->method != CJ_METHOD_CHEBYSHEV) return bfail(CJ_ERR_ARG, "batched and served solves use CJ_METHOD_CHEBYSHEV");
+    if (o->single_workgroup != 0) return bfail(CJ_ERR_ARG, "single_workgroup applies to single FP64 plans");
     if (o->inner_precision != CJ_INNER_AUTO && o->inner_precision != CJ_INNER_F32)
         return bfail(CJ_ERR_ARG, "batched and served solves run FP32 inner cycles (inner_precision 0 or CJ_INNER_F32)");
     if (o->M != 0 || o->inner_M != 0 || o->h != 0.0)

@@ -171,6 +171,17 @@ hipError_t launch_batch_residual(int stencil, const BatchProblem* probs, const B
 // out[s] <- sum of part[seg[s] .. seg[s+1]) for s < n_seg, fixed order.
 hipError_t launch_segmented_reduce(const double* part, const int* seg, int n_seg, double* out, hipStream_t stream);
 
+// Whole FP64 solve of a small 5- or 9-point grid in one workgroup with the
+// padded grid in LDS: A (padded iterate, staged, rings included) holds the
+// answer afterwards; out[0..3] <- status (0 ok, 1 stagnated, -4 max cycles,
+// -5 not finite), cycles, last relative residual, floor estimate.
+// lds_solve_fits: whether the grid fits (columns <= 1024, 16 rows per lane,
+// padded grid <= 160 KiB), with its lane mapping.
+bool lds_solve_fits(int stencil, int nx, int ny, int* wx, int* band, size_t* lds_bytes);
+hipError_t launch_lds_solve(int stencil, const Layout& L, double* A, const double* G, const double* w, int M,
+                            double gnorm, double tol, int cycles_pred, int max_cycles, double* out,
+                            hipStream_t stream);
+
 // out[0] <- sum of part[0 .. n) in a fixed order (one workgroup).
 hipError_t launch_reduce(const double* part, int n, double* out, hipStream_t stream);
 

@@ -885,6 +885,193 @@ __global__ __launch_bounds__(256) void stage_out_kernel(const double* __restrict
     u[(size_t)(y - 1 + fg) * ((size_t)nx + 2 * (size_t)fg) + (size_t)(x - 1 + fg)] = A[at<double>(pitch, x, y)];
 }
 
+// ------------------------------------------------------------ whole solve in one workgroup
+// Small grids (5- and 9-point): one workgroup of 1024 lanes holds the padded
+// grid (rows and columns -1 .. n + 2) in LDS and runs the whole FP64 solve in
+// one launch, with the stopping rule of the host loop: at every cycle end the
+// residual of the iterate (a read-only pass, summed per lane in row order and
+// reduced in a fixed order), then the test, then M sweeps.  A sweep computes
+// the new values of a lane's nodes into registers from the LDS values,
+// waits at a barrier, and writes them back (an in-place Jacobi step: every
+// new value depends on old values only).  Each update is the expression of
+// sweep_kernel (window_residual, then fma(omega, r, u)) on the same values, so
+// the iterate has the same bits as the launched kernels; only the residual's
+// summation order differs.  Lane mapping: wave w covers columns
+// 1 + (w mod wx) * 64 + lane and the band w / wx of `band` rows; waves past
+// the last band only join the barriers.
+// out: [0] status (0 ok, 1 stagnated, -4 max cycles, -5 not finite),
+// [1] cycles, [2] last relative residual, [3] floor estimate.
+
+constexpr int kLdsSolveLanes = 1024;
+constexpr int kLdsSolveRows = 16;      // rows of a lane's band at most
+constexpr int kLdsSolveShortRows = 4;  // bands up to this height take the short variant
+
+// A double from lane - 1 (from_lower) or lane + 1 of the wave (whole-wave DPP
+// shifts); the first (last) lane gets 0.
+__device__ __forceinline__ double dpp_from_lower(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x138, 0xf, 0xf, true);        // wave_shr:1
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double dpp_from_upper(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x130, 0xf, 0xf, true);        // wave_shl:1
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int ST, int BR>
+__global__ __launch_bounds__(1024) void lds_solve_kernel(double* __restrict__ A, const double* __restrict__ G,
+                                                         const double* __restrict__ w, int M, int nx, int ny,
+                                                         int pitch, int wx, int band, double gnorm, double tol,
+                                                         int cycles_pred, int max_cycles,
+                                                         double* __restrict__ out) {
+    constexpr int R = Stencil<ST>::R;
+    static_assert(R == 1, "5- and 9-point stencils");
+    extern __shared__ double lds[];
+    const int P = nx + 4;                     // LDS row: columns -1 .. nx + 2
+    double* red = lds + (size_t)(ny + 4) * P; // 16 wave sums, then the decision
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int x = 1 + (wave % wx) * 64 + lane;
+    const int y0 = 1 + (wave / wx) * band;
+    const int y1 = min(y0 + band, ny + 1);
+    const bool in_band = wave / wx < 16 / wx && y0 <= ny;  // uniform per wave
+    const bool active = in_band && x <= nx;
+    // each lane holds its column's value of a row (lanes past the grid the
+    // ring column nx + 1, which the last interior lane needs from its
+    // neighbour); x - 1 and x + 1 come from the neighbouring lanes, across
+    // wave edges from LDS
+    const int xc = min(x, nx + 1);
+    const int xg = min(x, nx);
+    auto lat = [&](int xx, int yy) { return (size_t)(yy + 1) * P + (xx + 1); };
+    // summary {C, P_1} of row yy from the lane's value c there, as row_summary forms it
+    auto summarise = [&](double c, int yy, double (&sm)[2]) {
+        double l = dpp_from_lower(c), r = dpp_from_upper(c);
+        if (lane == 0) l = lds[lat(xc - 1, yy)];
+        if (lane == 63) r = lds[lat(min(xc + 1, nx + 2), yy)];
+        sm[0] = c;
+        sm[1] = l + r;
+    };
+    // r of the band's rows in order, handed to body(k, r, u) (rows held as a
+    // rolling window of summaries; the next row's value and g are loaded one
+    // row ahead)
+    // Bands of at most kLdsSolveShortRows rows keep their g in registers for
+    // the whole solve; taller bands read it again each sweep (from L2) so as
+    // not to spill.
+    constexpr bool kGInRegs = BR <= kLdsSolveShortRows;
+    double greg[kGInRegs ? BR : 1];
+    if constexpr (kGInRegs) {
+#pragma unroll
+        for (int k = 0; k < BR; ++k)
+            greg[k] = (in_band && y0 + k < y1) ? G[at<double>(pitch, xg, y0 + k)] : 0.0;
+    }
+    auto band_rows = [&](auto&& body) {
+        double sm[3][2];
+        summarise(lds[lat(xc, y0 - 1)], y0 - 1, sm[1]);
+        summarise(lds[lat(xc, y0)], y0, sm[2]);
+        double cn = lds[lat(xc, y0 + 1)];
+        double gn = 0.0;
+        if constexpr (!kGInRegs) gn = G[at<double>(pitch, xg, y0)];
+#pragma unroll
+        for (int k = 0; k < BR; ++k) {
+            if (y0 + k < y1) {
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    sm[r][0] = sm[r + 1][0];
+                    sm[r][1] = sm[r + 1][1];
+                }
+                summarise(cn, y0 + k + 1, sm[2]);
+                double g;
+                if constexpr (kGInRegs) {
+                    g = greg[k];
+                } else {
+                    g = gn;
+                }
+                if (y0 + k + 1 < y1) {
+                    cn = lds[lat(xc, y0 + k + 2)];
+                    if constexpr (!kGInRegs) gn = G[at<double>(pitch, xg, y0 + k + 1)];
+                }
+                body(k, summary_residual<double, ST>(sm, g, sm[1][0]), sm[1][0]);
+            }
+        }
+    };
+    for (int i = tid; i < (ny + 4) * P; i += kLdsSolveLanes) {
+        const int yy = i / P - 1, xx = i % P - 1;
+        lds[i] = A[at<double>(pitch, xx, yy)];
+    }
+    __syncthreads();
+
+    auto residual_sum = [&]() {
+        double acc = 0.0;
+        if (in_band)
+            band_rows([&](int, double res, double) {
+                if (active) acc = fmat<double>(res, res, acc);
+            });
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (lane == 0) red[wave] = acc;
+        __syncthreads();
+        double tot = 0.0;
+        if (tid == 0) {
+            tot = red[0];
+            for (int k = 1; k < kLdsSolveLanes / 64; ++k) tot += red[k];
+        }
+        return tot;
+    };
+
+    double prev = 0.0, rr = 0.0;
+    int c = 0, status = 0;
+    for (;;) {
+        const double r2 = residual_sum();
+        if (tid == 0) {
+            rr = __builtin_sqrt(r2) / gnorm;
+            int stop = 1;
+            if (!(rr - rr == 0.0)) {
+                status = -5;
+            } else if (rr <= tol) {
+                status = 0;
+            } else if (c >= 1 && c >= cycles_pred && rr > 0.5 * prev) {
+                status = 1;
+                out[3] = rr < prev ? rr : prev;
+            } else if (c >= max_cycles) {
+                status = -4;
+            } else {
+                stop = 0;
+            }
+            red[16] = stop ? 1.0 : 0.0;
+            prev = rr;
+        }
+        __syncthreads();
+        const bool stop = red[16] != 0.0;
+        __syncthreads();   // every lane has read the decision before the slots are reused
+        if (stop) break;
+        for (int j = 0; j < M; ++j) {
+            const double omega = w[j];
+            double un[BR];
+            if (in_band)
+                band_rows([&](int k, double res, double u) { un[k] = fmat<double>(omega, res, u); });
+            __syncthreads();
+            if (active) {
+#pragma unroll
+                for (int k = 0; k < BR; ++k)
+                    if (y0 + k < y1) lds[lat(x, y0 + k)] = un[k];
+            }
+            __syncthreads();
+        }
+        ++c;
+    }
+    for (int i = tid; i < nx * ny; i += kLdsSolveLanes) {
+        const int yy = i / nx + 1, xx = i % nx + 1;
+        A[at<double>(pitch, xx, yy)] = lds[lat(xx, yy)];
+    }
+    if (tid == 0) {
+        out[0] = (double)status;
+        out[1] = (double)c;
+        out[2] = rr;
+    }
+}
+
 // ------------------------------------------------------------ reduction / apply
 
 __global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ part, int n, double* __restrict__ out) {
@@ -1317,6 +1504,53 @@ hipError_t launch_batch_residual(int stencil, const BatchProblem* probs, const B
 hipError_t launch_segmented_reduce(const double* part, const int* seg, int n_seg, double* out, hipStream_t stream) {
     if (n_seg <= 0) return hipSuccess;
     hipLaunchKernelGGL(segmented_reduce_kernel, dim3(n_seg), dim3(256), 0, stream, part, seg, out);
+    return hipGetLastError();
+}
+
+bool lds_solve_fits(int stencil, int nx, int ny, int* wx, int* band, size_t* lds_bytes) {
+    if (stencil != 5 && stencil != 9) return false;
+    const int w = (nx + 63) / 64;
+    if (w > kLdsSolveLanes / 64) return false;
+    const int bands = (kLdsSolveLanes / 64) / w;
+    const int b = (ny + bands - 1) / bands;
+    if (b > kLdsSolveRows) return false;
+    const size_t bytes = ((size_t)(nx + 4) * (size_t)(ny + 4) + 17) * sizeof(double);
+    if (bytes > 160 * 1024) return false;
+    if (wx) *wx = w;
+    if (band) *band = b;
+    if (lds_bytes) *lds_bytes = bytes;
+    return true;
+}
+
+hipError_t launch_lds_solve(int stencil, const Layout& L, double* A, const double* G, const double* w, int M,
+                            double gnorm, double tol, int cycles_pred, int max_cycles, double* out,
+                            hipStream_t stream) {
+    int wx = 0, band = 0;
+    size_t bytes = 0;
+    if (!lds_solve_fits(stencil, L.nx, L.ny, &wx, &band, &bytes) || L.frame > 1) return hipErrorInvalidValue;
+    static bool attr_set[4] = {false, false, false, false};
+    const bool short_band = band <= kLdsSolveShortRows;
+    const void* fn = stencil == 5 ? (short_band ? (const void*)lds_solve_kernel<5, kLdsSolveShortRows>
+                                                : (const void*)lds_solve_kernel<5, kLdsSolveRows>)
+                                  : (short_band ? (const void*)lds_solve_kernel<9, kLdsSolveShortRows>
+                                                : (const void*)lds_solve_kernel<9, kLdsSolveRows>);
+    const int si = (stencil == 5 ? 0 : 2) + (short_band ? 0 : 1);
+    if (!attr_set[si]) {
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set[si] = true;
+    }
+#define CJ_LDS_SOLVE(ST, BR)                                                                                  \
+    hipLaunchKernelGGL((lds_solve_kernel<ST, BR>), dim3(1), dim3(kLdsSolveLanes), bytes, stream, A, G, w, M, \
+                       L.nx, L.ny, L.pitch, wx, band, gnorm, tol, cycles_pred, max_cycles, out)
+    if (stencil == 5) {
+        if (short_band) CJ_LDS_SOLVE(5, kLdsSolveShortRows);
+        else CJ_LDS_SOLVE(5, kLdsSolveRows);
+    } else {
+        if (short_band) CJ_LDS_SOLVE(9, kLdsSolveShortRows);
+        else CJ_LDS_SOLVE(9, kLdsSolveRows);
+    }
+#undef CJ_LDS_SOLVE
     return hipGetLastError();
 }
 

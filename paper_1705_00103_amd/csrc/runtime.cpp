@@ -66,6 +66,10 @@ int radius(int stencil) { return stencil == 17 ? 2 : 1; }
 // value of eps32 * kappa_max / kappa_min (CJ_INNER_AUTO).
 constexpr double kInnerF64Above = 4.0;
 
+// The single-workgroup solve is chosen automatically up to this many rows per
+// lane (the kernel's short-band variant, whose g stays in registers).
+constexpr int kLdsAutoRows = 4;
+
 }  // namespace
 
 struct cj_plan_s {
@@ -109,6 +113,9 @@ struct cj_plan_s {
     // The plain launches of an FP64 cycle (all but the first, norm-fused one),
     // captured once as a graph on a private stream and replayed every cycle.
     bool use_graph = false;
+    // Small 5- and 9-point FP64 grids: the whole solve in one workgroup with
+    // the grid in LDS (launch_lds_solve).
+    bool use_lds = false;
     // Tile height of the blocked kernels: chosen on the device at the first
     // solve (tune_rows) unless the options fix it.
     bool tune_rows = false;
@@ -421,9 +428,41 @@ cj_status tune_tile_rows(cj_plan_s* p, hipStream_t stream) {
     return CJ_OK;
 }
 
+// The whole FP64 solve of a small grid in one workgroup (launch_lds_solve);
+// the answer is in A.
+cj_status solve_lds(cj_plan_s* p, double gnorm, hipStream_t stream, cj_result* r) {
+    CJ_HIP(hipEventRecord(p->ev[0], stream));
+    CJ_HIP(cj::launch_lds_solve(p->s.stencil, p->L, p->A, p->G, p->W, p->s.M, gnorm, p->s.tol, p->s.cycles_pred,
+                                p->max_cycles, p->scalar, stream));
+    CJ_HIP(hipEventRecord(p->ev[1], stream));
+    CJ_HIP(hipMemcpyAsync(p->host_slot, p->scalar, 4 * sizeof(double), hipMemcpyDeviceToHost, stream));
+    CJ_HIP(hipStreamSynchronize(stream));
+    float ms = 0.0f;
+    CJ_HIP(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
+    const int code = (int)p->host_slot[0];
+    r->cycles = (int)p->host_slot[1];
+    r->sweeps = (long long)r->cycles * p->s.M;
+    r->rel_residual = p->host_slot[2];
+    r->sweep_seconds = 1e-3 * (double)ms;
+    r->sweep_launches = 1;
+    switch (code) {
+    case 0: return CJ_OK;
+    case 1:
+        r->floor_estimate = p->host_slot[3];
+        g_last_error = "residual stagnated above tol (FP64 floor)";
+        return CJ_STAGNATED;
+    case -4: return fail(CJ_ERR_NOT_CONVERGED, "max_cycles reached");
+    default: return fail(CJ_ERR_NONFINITE, "residual is not finite (u has a NaN or Inf)");
+    }
+}
+
 // The FP64 CJM loop (see the file comment).  On return *out_buf is the buffer
 // holding the answer.
 cj_status solve_f64(cj_plan_s* p, double gnorm, hipStream_t stream, cj_result* r, double** out_buf) {
+    if (p->use_lds) {
+        *out_buf = p->A;
+        return solve_lds(p, gnorm, stream, r);
+    }
     cj_status st;
     double* cur = p->A;
     double* nxt = p->B;
@@ -778,6 +817,23 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol, const cj_o
     if (o.graph < -1 || o.graph > 1) {
         delete p;
         return fail(CJ_ERR_ARG, "graph must be -1, 0 or 1");
+    }
+    if (o.single_workgroup < -1 || o.single_workgroup > 1) {
+        delete p;
+        return fail(CJ_ERR_ARG, "single_workgroup must be -1, 0 or 1");
+    }
+    {
+        int band = 0;
+        const bool fits = !mixed && cj::lds_solve_fits(stencil, nx, ny, nullptr, &band, nullptr);
+        if (o.single_workgroup == 1 && !fits) {
+            delete p;
+            return fail(CJ_ERR_ARG, "single_workgroup = 1 needs an FP64 5- or 9-point plan whose padded grid fits "
+                                    "in LDS (at most 1024 columns, 16 rows per lane, 160 KiB)");
+        }
+        // on by default only where one workgroup beat the launched cycles:
+        // bands of at most kLdsAutoRows rows per lane (one CU's FP64 and LDS
+        // rates fall behind the whole chip's beyond that)
+        p->use_lds = fits && (o.single_workgroup == 1 || (o.single_workgroup == 0 && band <= kLdsAutoRows));
     }
     {
         // graphs need whole K-launches per cycle with an even launch count

@@ -204,3 +204,16 @@ def test_refinement_inner_precision_on_the_host():
     code = L.cj_batch_create(1, (ctypes.c_int * 1)(10), (ctypes.c_int * 1)(10), (ctypes.c_int * 1)(9),
                              (ctypes.c_double * 1)(1e-8), ctypes.byref(opt), ctypes.byref(h))
     assert code == cj.CJ_ERR_ARG and not h.value
+
+
+def test_single_workgroup_option_on_the_host():
+    cj.plan(128, 128, 9, 1e-10, single_workgroup=1)
+    cj.plan(1000, 10, 5, 1e-10, single_workgroup=1)
+    for args in ((129, 129, 9), (1025, 2, 9), (64, 300, 9), (128, 128, 17)):
+        with pytest.raises(cj.CJError) as e:
+            cj.plan(*args, 1e-10, single_workgroup=1)
+        assert e.value.code == cj.CJ_ERR_ARG
+    with pytest.raises(cj.CJError):
+        cj.plan(128, 128, 9, 1e-10, precision=cj.F32_REFINE, single_workgroup=1)
+    with pytest.raises(cj.CJError):
+        cj.plan(64, 64, 9, 1e-10, single_workgroup=2)

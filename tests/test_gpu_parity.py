@@ -269,8 +269,9 @@ def test_graph_replayed_cycles_match_eager_launches(torch_cuda, st, nx, ny):
     solves, with eager work (another plan's solve) in between."""
     torch = torch_cuda
     f = _dev(torch, inputs.gaussian_bumps_rhs(nx, ny, seed=31))
-    pg = cj.plan(nx, ny, st, 1e-10, graph=1)
-    pe = cj.plan(nx, ny, st, 1e-10, graph=-1)
+    # launched cycles (small grids otherwise take the single-workgroup solve)
+    pg = cj.plan(nx, ny, st, 1e-10, graph=1, single_workgroup=-1)
+    pe = cj.plan(nx, ny, st, 1e-10, graph=-1, single_workgroup=-1)
     ref = None
     for rep in range(3):
         ue = torch.zeros(ny, nx, dtype=torch.float64, device="cuda")
@@ -327,3 +328,42 @@ def test_extreme_aspect_ratios(torch_cuda, st, nx, ny):
         p.destroy()
     assert np.array_equal(outs[0], outs[1])
     assert np.abs(outs[0] - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+SMALL = [(9, 128, 128, False, "chebyshev"), (5, 128, 128, False, "chebyshev"), (9, 1, 1, False, "chebyshev"),
+         (9, 3, 2, False, "chebyshev"), (5, 100, 37, True, "chebyshev"), (9, 1000, 10, False, "chebyshev"),
+         (9, 64, 256, True, "chebyshev"), (5, 70, 70, False, "jacobi"), (9, 130, 64, False, "chebyshev"),
+         # bands of at most four rows: the variant that keeps g in registers
+         (9, 32, 32, True, "chebyshev"), (5, 64, 64, False, "chebyshev"), (9, 256, 16, False, "jacobi"),
+         (5, 65, 61, False, "chebyshev")]
+
+
+@pytest.mark.parametrize("st,nx,ny,frame,method", SMALL)
+def test_single_workgroup_solve_matches_launched_cycles(torch_cuda, st, nx, ny, frame, method):
+    """Small 5- and 9-point grids solved in one workgroup with the grid in LDS
+    give the bits, status and cycle count of the launched cycles (the residual
+    that decides is summed in another order, so it agrees to rounding), and
+    the oracle's solution."""
+    torch = torch_cuda
+    tol = 1e-10
+    f = inputs.gaussian_bumps_rhs(nx, ny, seed=40 + nx + ny)
+    bc = cj.BC_FRAME if frame else cj.BC_ZERO
+    obc = cjm.BC_FRAME if frame else cjm.BC_ZERO
+    m = cj.JACOBI if method == "jacobi" else cj.CHEBYSHEV
+    u0 = inputs.expxy_frame(nx, ny, 1) if frame else np.zeros((ny, nx))
+    out = []
+    for sw in (1, -1):
+        p = cj.plan(nx, ny, st, tol, bc=bc, method=m, single_workgroup=sw)
+        u = _dev(torch, u0)
+        r = cj.solve(p, _dev(torch, f), u)
+        out.append((r, _host(u)))
+    (r1, u1), (r2, u2) = out
+    print("%d-point %dx%d %s: %s %d cycles, relres %.6e / %.6e, %.3f / %.3f ms"
+          % (st, nx, ny, method, r1["status"], r1["cycles"], r1["rel_residual"], r2["rel_residual"],
+             r1["seconds"] * 1e3, r2["seconds"] * 1e3), flush=True)
+    assert (r1["status"], r1["cycles"], r1["sweeps"]) == (r2["status"], r2["cycles"], r2["sweeps"])
+    assert np.array_equal(u1, u2)
+    assert abs(r1["rel_residual"] - r2["rel_residual"]) <= 1e-9 * r2["rel_residual"] + 1e-15
+    ref = cjm.solve(f, nx, ny, st, tol, u0=u0 if frame else None, bc=obc, method=method)
+    assert (r1["status"], r1["cycles"]) == (ref["status"], ref["cycles"])
+    assert _rel(u1, ref["u"]) <= REL_L2
