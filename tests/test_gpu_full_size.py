@@ -190,6 +190,42 @@ def test_c2_8192_solve_and_blocked_seams(torch_cuda, st):
     assert dev <= 1e-12 * scale
 
 
+def test_c3_16384_blocked_seams(torch_cuda):
+    """The largest grid (16384^2, 9-point, the C3 size) in the plain FP64 path's own
+    launch configuration: one cycle tunes the tile height, then 3K + 3 sweeps are
+    bitwise equal to single sweeps and match the oracle at the blocked kernel's
+    strip and tile seams."""
+    torch = torch_cuda
+    n, st, tol = 16384, 9, 1e-10
+    _say("case: 16384^2 9-point, one cycle (tile tuning)")
+    f = inputs.gaussian_bumps_rhs(n, n, seed=1705 + st)
+    fd = _dev(torch, f)
+    p = cj.plan(n, n, st, tol, max_cycles=1)
+    u = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+    r = cj.solve(p, fd, u)
+    K, rows, wg = p.refresh_launch_info()
+    _say("K %d rows %d workgroups %d: status %s after %d cycle(s), relres %.3e"
+         % (K, rows, wg, r["status"], r["cycles"], r["rel_residual"]))
+    assert r["status"] == "not_converged" and r["cycles"] == 1 and np.isfinite(r["rel_residual"])
+    nsw = 3 * K + 3
+    _say("case: 16384^2 9-point, %d sweeps sampled at seams" % nsw)
+    u0 = inputs.random_field(n, n, seed=19, scale=1e-3)
+    u.copy_(_dev(torch, u0))
+    cj.sweeps(p, fd, u, nsw)
+    got = _host(u)
+    p_single = cj.plan(n, n, st, tol, sweeps_per_launch=1)
+    u.copy_(_dev(torch, u0))
+    cj.sweeps(p_single, fd, u, nsw)
+    assert np.array_equal(_host(u), got)
+    pts = _seam_points(n, K, 1, rows, np.random.default_rng(n + st))
+    ref = cjm.sampled_sweeps(f, u0, n, n, st, tol, nsw, pts)
+    vals = np.array([got[j - 1, i - 1] for (i, j) in pts])
+    dev = np.abs(vals - ref).max()
+    scale = np.abs(ref).max()
+    _say("%d sampled nodes: max |GPU - oracle| %.3e of scale %.3e" % (len(pts), dev, scale))
+    assert dev <= 1e-12 * scale
+
+
 C3_SHAPES = [pytest.param(8192, 8192, id="8192x8192"), pytest.param(16384, 4096, id="16384x4096")]
 
 
