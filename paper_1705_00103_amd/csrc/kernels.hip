@@ -1528,18 +1528,16 @@ hipError_t launch_lds_solve(int stencil, const Layout& L, double* A, const doubl
     int wx = 0, band = 0;
     size_t bytes = 0;
     if (!lds_solve_fits(stencil, L.nx, L.ny, &wx, &band, &bytes) || L.frame > 1) return hipErrorInvalidValue;
-    static bool attr_set[4] = {false, false, false, false};
     const bool short_band = band <= kLdsSolveShortRows;
     const void* fn = stencil == 5 ? (short_band ? (const void*)lds_solve_kernel<5, kLdsSolveShortRows>
                                                 : (const void*)lds_solve_kernel<5, kLdsSolveRows>)
                                   : (short_band ? (const void*)lds_solve_kernel<9, kLdsSolveShortRows>
                                                 : (const void*)lds_solve_kernel<9, kLdsSolveRows>);
-    const int si = (stencil == 5 ? 0 : 2) + (short_band ? 0 : 1);
-    if (!attr_set[si]) {
-        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr_set[si] = true;
-    }
+    // the dynamic LDS limit is a property of the function on the current
+    // device: set it at every launch (one host call per solve), so that every
+    // device the library runs on gets it
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
 #define CJ_LDS_SOLVE(ST, BR)                                                                                  \
     hipLaunchKernelGGL((lds_solve_kernel<ST, BR>), dim3(1), dim3(kLdsSolveLanes), bytes, stream, A, G, w, M, \
                        L.nx, L.ny, L.pitch, wx, band, gnorm, tol, cycles_pred, max_cycles, out)
