@@ -124,7 +124,7 @@ cj_status plan_problem(Problem& p, int Kreq, int tile_rows) {
     p.T = cj::make_tiles(p.nx, p.ny, 16);
     p.T.width = 256;
     p.T.tiles_x = (p.nx + 255) / 256;
-    p.TK = cj::make_tiles_k(p.nx, p.ny, p.K, R, tile_rows > 0 ? tile_rows : 64);
+    p.TK = cj::make_tiles_k(p.nx, p.ny, p.K, R, tile_rows > 0 ? tile_rows : 64, sizeof(float));
     size_t off = 0;
     p.off_u = off;  off += align256(p.L.elems * sizeof(double));
     p.off_g = off;  off += align256(p.L.elems * sizeof(double));
@@ -408,7 +408,7 @@ public:
     static int group_of(int stencil) { return stencil == 5 ? 0 : stencil == 9 ? 1 : 2; }
 
     void set_rows(Problem* p, int rows) {
-        p->TK = cj::make_tiles_k(p->nx, p->ny, p->K, p->stencil == 17 ? 2 : 1, rows);
+        p->TK = cj::make_tiles_k(p->nx, p->ny, p->K, p->stencil == 17 ? 2 : 1, rows, sizeof(float));
         desc(p).strips_x = p->TK.tiles_x;
         desc(p).rows_k = p->TK.rows;
     }
@@ -569,7 +569,7 @@ public:
                         long long tiles = 0;
                         for (Problem* p : live)
                             if (p->state == State::Active)
-                                tiles += cj::make_tiles_k(p->nx, p->ny, p->K, p->stencil == 17 ? 2 : 1, r).count();
+                                tiles += cj::make_tiles_k(p->nx, p->ny, p->K, p->stencil == 17 ? 2 : 1, r, sizeof(float)).count();
                         return tiles;
                     };
                     int rows = 64;
@@ -591,7 +591,7 @@ public:
                     }
                     for (Problem* p : live)
                         if (p->state == State::Active && p->TK.rows != std::min(rows, p->ny)) {
-                            p->TK = cj::make_tiles_k(p->nx, p->ny, p->K, p->stencil == 17 ? 2 : 1, rows);
+                            p->TK = cj::make_tiles_k(p->nx, p->ny, p->K, p->stencil == 17 ? 2 : 1, rows, sizeof(float));
                             desc(p).strips_x = p->TK.tiles_x;
                             desc(p).rows_k = p->TK.rows;
                         }

@@ -63,9 +63,19 @@ struct Tiles {
 
 Tiles make_tiles(int nx, int ny, int rows_request);
 
-// Geometry of the temporally blocked kernel: strips of 256 - 2KR output
-// columns (tiles_x strips) by tiles of `rows` output rows.
-Tiles make_tiles_k(int nx, int ny, int K, int R, int rows_request);
+// Lanes of the temporally blocked kernel's workgroup, one per column of its
+// strip.  FP64 radius-1 stencils at K >= 10 (the large-grid default) take 512
+// lanes, one workgroup per CU: half the strip overlap of 256 lanes (2KR
+// columns of 512), measured 5-6% faster per sweep at 8192^2; the 17-point
+// kernel lost 9% that way, and smaller K serve grids where wider strips would
+// leave CUs idle.
+__host__ __device__ constexpr int strip_lanes(int R, int K, int elem_bytes) {
+    return (elem_bytes == 8 && R == 1 && K >= 10) ? 512 : 256;
+}
+
+// Geometry of the temporally blocked kernel: strips of strip_lanes - 2KR
+// output columns (tiles_x strips) by tiles of `rows` output rows.
+Tiles make_tiles_k(int nx, int ny, int K, int R, int rows_request, int elem_bytes);
 
 // ---------------------------------------------------------------- batches
 // Device descriptor of one problem of a batch (FP32 inner sweeps inside FP64

@@ -223,10 +223,10 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
     return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
 }
 
-// Sum over the workgroup (blockDim.x = 64 * waves, waves <= 4), fixed order.
+// Sum over the workgroup (blockDim.x = 64 * waves, waves <= 8), fixed order.
 // The result is valid in thread 0.
 __device__ __forceinline__ double block_sum(double v) {
-    __shared__ double ws[4];
+    __shared__ double ws[8];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     const int wave = threadIdx.x >> 6;
@@ -350,7 +350,8 @@ template <typename T, int ST, int K>
 struct March {
     static constexpr int R = Stencil<ST>::R;
     static constexpr int W = 2 * R + 1;
-    static constexpr int WOUT = 256 - 2 * K * R;
+    static constexpr int SW = strip_lanes(R, K, sizeof(T));   // lanes = strip columns
+    static constexpr int WOUT = SW - 2 * K * R;
     // level-0 rows are fetched PD row steps ahead (a row step is shorter than
     // the HBM latency under load).  Measured at 8192^2: 3-row windows gain
     // from 3 steps in FP32 and 2 in FP64 (9-point K = 8: 75.3 -> 70.1 us per
@@ -383,7 +384,7 @@ struct March {
 // end.  The level-0 row of this step was prefetched PD steps earlier into
 // prefetch slot J % PD, which this step refills with the row PD steps ahead.
 template <typename T, int ST, int K, bool NORM, bool REFL, bool EDGE, bool EY, int J>
-__device__ __forceinline__ void march_step(March<T, ST, K>& S, T (*xch)[March<T, ST, K>::W][256],
+__device__ __forceinline__ void march_step(March<T, ST, K>& S, T (*xch)[March<T, ST, K>::W][March<T, ST, K>::SW],
                                            const T* __restrict__ uin, T* __restrict__ uout, const T* __restrict__ g,
                                            const T (&om)[K], int t, int ybase, int x, int xg, bool out_col, int Y0,
                                            int Y1, int nx, int ny, int pitch, double& acc) {
@@ -473,7 +474,7 @@ __device__ __forceinline__ void march_step(March<T, ST, K>& S, T (*xch)[March<T,
 
 // Row steps t + J, t + J + 1, ..., t + U - 1 (compile-time phases).
 template <typename T, int ST, int K, bool NORM, bool REFL, bool EDGE, bool EY, int J>
-__device__ __forceinline__ void march_steps(March<T, ST, K>& S, T (*xch)[March<T, ST, K>::W][256],
+__device__ __forceinline__ void march_steps(March<T, ST, K>& S, T (*xch)[March<T, ST, K>::W][March<T, ST, K>::SW],
                                             const T* __restrict__ uin, T* __restrict__ uout,
                                             const T* __restrict__ g, const T (&om)[K], int t, int ybase, int x,
                                             int xg, bool out_col, int Y0, int Y1, int nx, int ny, int pitch,
@@ -486,7 +487,7 @@ __device__ __forceinline__ void march_steps(March<T, ST, K>& S, T (*xch)[March<T
 }
 
 template <typename T, int ST, int K, bool NORM, bool REFL, bool EDGE, bool EY>
-__device__ __forceinline__ void march(March<T, ST, K>& S, T (*xch)[March<T, ST, K>::W][256],
+__device__ __forceinline__ void march(March<T, ST, K>& S, T (*xch)[March<T, ST, K>::W][March<T, ST, K>::SW],
                                       const T* __restrict__ uin, T* __restrict__ uout, const T* __restrict__ g,
                                       const T (&om)[K], int ybase, int steps, int x, int xg, bool out_col, int Y0,
                                       int Y1, int nx, int ny, int pitch, double& acc) {
@@ -505,7 +506,8 @@ __device__ __forceinline__ void sweepk_tile(const T* __restrict__ uin, T* __rest
     constexpr int R = MS::R;
     constexpr int W = MS::W;
     constexpr int WOUT = MS::WOUT;
-    __shared__ T xch[K > 1 ? K - 1 : 1][W][256];
+    constexpr int SW = MS::SW;
+    __shared__ T xch[K > 1 ? K - 1 : 1][W][SW];
 
     const int tid = threadIdx.x;
     const int sx = tile % strips_x, sy = tile / strips_x;
@@ -516,7 +518,7 @@ __device__ __forceinline__ void sweepk_tile(const T* __restrict__ uin, T* __rest
     const bool out_col = tid >= K * R && tid < K * R + WOUT && x >= 1 && x <= nx;
     const int xg = min(max(x, 1), nx);     // column for g (only interior columns matter)
     // Does the halo of this workgroup reach beyond the interior?  (uniform)
-    const bool edge_x = (X0 - K * R < 1) || (X0 - K * R + 255 > nx);
+    const bool edge_x = (X0 - K * R < 1) || (X0 - K * R + SW - 1 > nx);
     const bool edge_y = (Y0 - K * R < 1) || (Y1 - 1 + K * R > ny);
 
     MS S;
@@ -530,7 +532,7 @@ __device__ __forceinline__ void sweepk_tile(const T* __restrict__ uin, T* __rest
             else if (col == -1) { idx = tid + dx + 2; sg = -1; }
             else if (col == nx + 2) { idx = tid + dx - 2; sg = -1; }
         }
-        S.xsrc[c] = min(max(idx, 0), 255);
+        S.xsrc[c] = min(max(idx, 0), SW - 1);
         S.xsgn[c] = sg;
     }
     T om[K];
@@ -574,7 +576,7 @@ __device__ __forceinline__ void sweepk_tile(const T* __restrict__ uin, T* __rest
 }
 
 template <typename T, int ST, int K, bool NORM, bool REFL>
-__global__ __launch_bounds__(256) void sweepk_kernel(const T* __restrict__ uin, T* __restrict__ uout,
+__global__ __launch_bounds__((March<T, ST, K>::SW)) void sweepk_kernel(const T* __restrict__ uin, T* __restrict__ uout,
                                                      const T* __restrict__ g, const T* __restrict__ w, int widx,
                                                      int nx, int ny, int pitch, int strips_x, int rows,
                                                      double* __restrict__ part) {
@@ -1223,10 +1225,10 @@ template <typename T, int ST, int K, bool NORM>
 void launch_k_refl(const Layout& L, const Tiles& Tl, const T* uin, T* uout, const T* g, const T* w, int widx,
                    double* part, hipStream_t s) {
     if (ST == 17 && L.frame == 0)
-        hipLaunchKernelGGL((sweepk_kernel<T, ST, K, NORM, true>), dim3(Tl.count()), dim3(256), 0, s, uin, uout, g,
+        hipLaunchKernelGGL((sweepk_kernel<T, ST, K, NORM, true>), dim3(Tl.count()), dim3(March<T, ST, K>::SW), 0, s, uin, uout, g,
                            w, widx, L.nx, L.ny, L.pitch, Tl.tiles_x, Tl.rows, part);
     else
-        hipLaunchKernelGGL((sweepk_kernel<T, ST, K, NORM, false>), dim3(Tl.count()), dim3(256), 0, s, uin, uout, g,
+        hipLaunchKernelGGL((sweepk_kernel<T, ST, K, NORM, false>), dim3(Tl.count()), dim3(March<T, ST, K>::SW), 0, s, uin, uout, g,
                            w, widx, L.nx, L.ny, L.pitch, Tl.tiles_x, Tl.rows, part);
 }
 
@@ -1339,8 +1341,10 @@ namespace {
 template <typename T, int ST, int K>
 hipError_t occupancy_k(bool refl, int* blocks) {
     if (ST == 17 && refl)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweepk_kernel<T, ST, K, false, true>, 256, 0);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweepk_kernel<T, ST, K, false, false>, 256, 0);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweepk_kernel<T, ST, K, false, true>,
+                                                           March<T, ST, K>::SW, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweepk_kernel<T, ST, K, false, false>,
+                                                           March<T, ST, K>::SW, 0);
 }
 }  // namespace
 
@@ -1587,9 +1591,9 @@ Layout make_layout(int nx, int ny, int elem_bytes, int frame) {
     return L;
 }
 
-Tiles make_tiles_k(int nx, int ny, int K, int R, int rows_request) {
+Tiles make_tiles_k(int nx, int ny, int K, int R, int rows_request, int elem_bytes) {
     Tiles T;
-    T.width = 256 - 2 * K * R;               // output columns per strip
+    T.width = strip_lanes(R, K, elem_bytes) - 2 * K * R;   // output columns per strip
     T.tiles_x = (nx + T.width - 1) / T.width;
     int rows = rows_request > 0 ? rows_request : 128;
     if (rows_request <= 0)

@@ -143,8 +143,11 @@ struct cj_plan_s {
         if (tune_rows && K > 1) {
             // room for the flattest tile the first solve may choose
             const bool small = (long long)s.nx * s.ny <= (1LL << 18);
-            const int m = cj::make_tiles_k(s.nx, s.ny, K, s.stencil == 17 ? 2 : 1, small ? 1 : kTuneRows[0]).count();
-            if (m > n) n = m;
+            const int R = s.stencil == 17 ? 2 : 1;
+            for (int eb : {4, 8}) {
+                const int m = cj::make_tiles_k(s.nx, s.ny, K, R, small ? 1 : kTuneRows[0], eb).count();
+                if (m > n) n = m;
+            }
         }
         return n;
     }
@@ -276,7 +279,8 @@ cj_status enqueue_sweeps(cj_plan_s* p, int M, int K, const cj::Layout& L, const 
             CJ_HIP(cj::launch_sweepk(p->s.stencil, K, L, TK, *cur, *nxt, g, w, w0, part, stream));
             if (norm) *norm_parts = TK.count();
         } else if (k > 1 && !norm && cj::sweepk_supported(p->s.stencil, (int)k, L.elem_bytes)) {
-            const cj::Tiles Tk = cj::make_tiles_k(L.nx, L.ny, (int)k, radius(p->s.stencil), p->opt.tile_rows);
+            const cj::Tiles Tk =
+                cj::make_tiles_k(L.nx, L.ny, (int)k, radius(p->s.stencil), p->opt.tile_rows, L.elem_bytes);
             CJ_HIP(cj::launch_sweepk(p->s.stencil, (int)k, L, Tk, *cur, *nxt, g, w, w0, nullptr, stream));
         } else {
             k = 1;
@@ -347,6 +351,7 @@ cj_status tune_tile_rows(cj_plan_s* p, hipStream_t stream) {
     const int K = mixed ? p->K32 : p->K;
     if (K <= 1) return CJ_OK;
     const int R = radius(p->s.stencil);
+    const int eb = mixed ? (int)sizeof(float) : (int)sizeof(double);
     const int nx = p->s.nx, ny = p->s.ny;
     long long slots = 0;   // workgroups of the blocked kernel the device holds at once
     int cus = 0;
@@ -367,7 +372,7 @@ cj_status tune_tile_rows(cj_plan_s* p, hipStream_t stream) {
         // launches).
         if (cus <= 0) return CJ_OK;
         const long long per_round = cus;
-        const int strips = cj::make_tiles_k(nx, ny, K, R, 1).tiles_x;
+        const int strips = cj::make_tiles_k(nx, ny, K, R, 1, eb).tiles_x;
         long long best_cost = -1;
         int best_rows = 0;
         for (int rows = 1; rows <= 128 && rows <= ny; ++rows) {
@@ -378,7 +383,7 @@ cj_status tune_tile_rows(cj_plan_s* p, hipStream_t stream) {
                 best_rows = rows;
             }
         }
-        (mixed ? p->TK32 : p->TK) = cj::make_tiles_k(nx, ny, K, R, best_rows);
+        (mixed ? p->TK32 : p->TK) = cj::make_tiles_k(nx, ny, K, R, best_rows, eb);
         return CJ_OK;
     }
     // candidates: a fixed ladder, plus the heights whose tile count just fills
@@ -386,7 +391,7 @@ cj_status tune_tile_rows(cj_plan_s* p, hipStream_t stream) {
     std::vector<int> cand(std::begin(cj_plan_s::kTuneRows), std::end(cj_plan_s::kTuneRows));
     {
         if (slots > 0) {
-            const int strips = cj::make_tiles_k(nx, ny, K, R, cj_plan_s::kTuneRows[0]).tiles_x;
+            const int strips = cj::make_tiles_k(nx, ny, K, R, cj_plan_s::kTuneRows[0], eb).tiles_x;
             for (int r = 1; r <= 8; ++r) {
                 const long long ty = r * slots / strips;
                 if (ty < 1) continue;
@@ -401,7 +406,7 @@ cj_status tune_tile_rows(cj_plan_s* p, hipStream_t stream) {
     float best_ms = -1.0f;
     for (int rows : cand) {
         if (rows > ny) break;
-        const cj::Tiles Tc = cj::make_tiles_k(nx, ny, K, R, rows);
+        const cj::Tiles Tc = cj::make_tiles_k(nx, ny, K, R, rows, eb);
         float ms = -1.0f;   // the faster of two launches
         for (int rep = 0; rep < 2; ++rep) {
             float t = 0.0f;
@@ -800,12 +805,12 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol, const cj_o
         p->K = 1;
         p->K32 = o.sweeps_per_launch > 0 ? o.sweeps_per_launch : (stencil == 17 ? 4 : 8);
         p->T = cj::make_tiles(nx, ny, p->K32 == 1 ? o.tile_rows : 0);
-        if (p->K32 > 1) p->TK32 = cj::make_tiles_k(nx, ny, p->K32, R, o.tile_rows);
+        if (p->K32 > 1) p->TK32 = cj::make_tiles_k(nx, ny, p->K32, R, o.tile_rows, sizeof(float));
     } else {
         const bool large = (long long)nx * ny > (1LL << 22);
         p->K = o.sweeps_per_launch > 0 ? o.sweeps_per_launch : (stencil == 17 ? 4 : large ? 10 : 8);
         p->T = cj::make_tiles(nx, ny, p->K == 1 ? o.tile_rows : 0);
-        if (p->K > 1) p->TK = cj::make_tiles_k(nx, ny, p->K, R, o.tile_rows);
+        if (p->K > 1) p->TK = cj::make_tiles_k(nx, ny, p->K, R, o.tile_rows, sizeof(double));
     }
     p->D = centre_over_s(stencil) / (p->s.h * p->s.h);
     // the tile height is chosen at the first solve, once the device is known:

@@ -13,7 +13,7 @@ device, and every comparison below runs on that same plan afterwards.
 - 8192^2, all three stencils: the full solve against the exact discrete solution
   (type-I sine transform) and its residual recomputed by the oracle; then 3K + 3
   sweeps from a rough guess sampled on the blocked kernel's strip seams
-  (256 - 2KR output columns per strip) and tuned tile seams, each sample computed
+  (lanes - 2KR output columns per strip) and tuned tile seams, each sample computed
   by the oracle on its own domain of dependence, bar 1e-12 of the sample scale.
 - Mixed precision at 8192^2 and 16384 x 4096 (FP32 sweeps inside FP64
   refinement, and the double-double iterate of cj_solve_dd): the oracle's
@@ -116,12 +116,22 @@ def test_c2_4096_one_full_cycle_in_the_bench_launch_configuration(torch_cuda):
     assert abs(r1["rel_residual"] - rr) <= 1e-6 * rr + _residual_noise(st, f, got, n, n)
 
 
-def _seam_points(n, K, R, rows, rng):
-    """Nodes on both sides of the blocked kernel's strip seams (strips of 256 - 2KR
-    output columns; also those of a K = 3 launch, which ends a short run) and of
-    the tile seams (tuned height, and the 128-row default of the shorter launch),
-    plus corners and random nodes."""
-    wout = 256 - 2 * K * R
+def _strip_lanes(n, K, R, rows, workgroups):
+    """Lanes per workgroup of the blocked launch (256 or 512 columns per strip),
+    read off the plan's workgroup count: strips of lanes - 2KR output columns
+    by tiles of `rows` rows."""
+    fits = [w for w in (256, 512)
+            if -(-n // (w - 2 * K * R)) * -(-n // rows) == workgroups]
+    assert len(fits) == 1, (n, K, R, rows, workgroups)
+    return fits[0]
+
+
+def _seam_points(n, K, R, rows, rng, lanes=256):
+    """Nodes on both sides of the blocked kernel's strip seams (strips of
+    lanes - 2KR output columns; also those of a K = 3 launch, which ends a short
+    run in 256-lane strips) and of the tile seams (tuned height, and the 128-row
+    default of the shorter launch), plus corners and random nodes."""
+    wout = lanes - 2 * K * R
     xs = set()
     for w in (wout, 256 - 2 * 3 * R):
         for k in (1, 2, 5, n // w - 1, n // w):
@@ -181,7 +191,9 @@ def test_c2_8192_solve_and_blocked_seams(torch_cuda, st):
     u.copy_(_dev(torch, u0))
     cj.sweeps(p_single, fd, u, nsw)
     assert np.array_equal(_host(u), got)
-    pts = _seam_points(n, K, R, rows, np.random.default_rng(n + st))
+    lanes = _strip_lanes(n, K, R, rows, wg)
+    pts = _seam_points(n, K, R, rows, np.random.default_rng(n + st), lanes)
+    _say("strips of %d lanes (%d output columns), %d-row tiles" % (lanes, lanes - 2 * K * R, rows))
     ref = cjm.sampled_sweeps(f, u0, n, n, st, tol, nsw, pts)
     vals = np.array([got[j - 1, i - 1] for (i, j) in pts])
     dev = np.abs(vals - ref).max()
@@ -217,7 +229,9 @@ def test_c3_16384_blocked_seams(torch_cuda):
     u.copy_(_dev(torch, u0))
     cj.sweeps(p_single, fd, u, nsw)
     assert np.array_equal(_host(u), got)
-    pts = _seam_points(n, K, 1, rows, np.random.default_rng(n + st))
+    lanes = _strip_lanes(n, K, 1, rows, wg)
+    pts = _seam_points(n, K, 1, rows, np.random.default_rng(n + st), lanes)
+    _say("strips of %d lanes (%d output columns), %d-row tiles" % (lanes, lanes - 2 * K, rows))
     ref = cjm.sampled_sweeps(f, u0, n, n, st, tol, nsw, pts)
     vals = np.array([got[j - 1, i - 1] for (i, j) in pts])
     dev = np.abs(vals - ref).max()
