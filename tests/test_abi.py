@@ -217,3 +217,19 @@ def test_single_workgroup_option_on_the_host():
         cj.plan(128, 128, 9, 1e-10, precision=cj.F32_REFINE, single_workgroup=1)
     with pytest.raises(cj.CJError):
         cj.plan(64, 64, 9, 1e-10, single_workgroup=2)
+
+
+@pytest.mark.parametrize("st,precision,K,lanes", [
+    (9, "f64", 10, 512), (5, "f64", 10, 512), (9, "f64", 8, 256), (17, "f64", 4, 256),
+    (9, "f32", 8, 256), (5, "f32", 8, 256)])
+def test_blocked_strip_width_on_the_host(st, precision, K, lanes):
+    """The blocked kernel's strips: 512 lanes (512 - 2KR output columns) for FP64
+    radius-1 stencils at K = 10, 256 lanes otherwise; the plan's launch geometry
+    (before any solve: the default tile height) says which."""
+    n = 8192
+    prec = cj.F64 if precision == "f64" else cj.F32_REFINE
+    p = cj.plan(n, n, st, 1e-10, sweeps_per_launch=K, precision=prec, tile_rows=100)
+    k, rows, wg = p.refresh_launch_info()
+    R = 2 if st == 17 else 1
+    assert (k, rows) == (K, 100)
+    assert wg == -(-n // (lanes - 2 * K * R)) * -(-n // rows)
