@@ -136,9 +136,10 @@ typedef struct {
                                   (at most 1024 columns and 16 rows per lane of a 1024-lane
                                   workgroup, e.g. 128^2): run the whole solve in one launch of one
                                   workgroup holding the grid in LDS (the same iterates; the residual
-                                  is summed in another order); 0 = automatic (when it fits with
-                                  bands of at most 4 rows per lane, e.g. 64^2, the sizes where one
-                                  CU outpaces the launched cycles), 1 = required (CJ_ERR_ARG if it
+                                  is summed in another order); 0 = automatic (where one CU
+                                  outpaced the launched cycles: bands of at most 4 rows per lane,
+                                  e.g. 64^2; of at most 8 rows for 5 points, and for 9 points on
+                                  grids of at most 4096 points), 1 = required (CJ_ERR_ARG if it
                                   does not fit), -1 = never */
     int    reserved[2];        /* must be zero */
 } cj_options;

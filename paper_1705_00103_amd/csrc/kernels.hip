@@ -907,6 +907,7 @@ __global__ __launch_bounds__(256) void stage_out_kernel(const double* __restrict
 constexpr int kLdsSolveLanes = 1024;
 constexpr int kLdsSolveRows = 16;      // rows of a lane's band at most
 constexpr int kLdsSolveShortRows = 4;  // bands up to this height take the short variant
+constexpr int kLdsSolveMidRows = 8;    // and up to this height the middle one (g also in registers)
 
 // A double from lane - 1 (from_lower) or lane + 1 of the wave (whole-wave DPP
 // shifts); the first (last) lane gets 0.
@@ -958,10 +959,10 @@ __global__ __launch_bounds__(1024) void lds_solve_kernel(double* __restrict__ A,
     // r of the band's rows in order, handed to body(k, r, u) (rows held as a
     // rolling window of summaries; the next row's value and g are loaded one
     // row ahead)
-    // Bands of at most kLdsSolveShortRows rows keep their g in registers for
+    // Bands of at most kLdsSolveMidRows rows keep their g in registers for
     // the whole solve; taller bands read it again each sweep (from L2) so as
     // not to spill.
-    constexpr bool kGInRegs = BR <= kLdsSolveShortRows;
+    constexpr bool kGInRegs = BR <= kLdsSolveMidRows;
     double greg[kGInRegs ? BR : 1];
     if constexpr (kGInRegs) {
 #pragma unroll
@@ -1532,11 +1533,17 @@ hipError_t launch_lds_solve(int stencil, const Layout& L, double* A, const doubl
     int wx = 0, band = 0;
     size_t bytes = 0;
     if (!lds_solve_fits(stencil, L.nx, L.ny, &wx, &band, &bytes) || L.frame > 1) return hipErrorInvalidValue;
-    const bool short_band = band <= kLdsSolveShortRows;
-    const void* fn = stencil == 5 ? (short_band ? (const void*)lds_solve_kernel<5, kLdsSolveShortRows>
-                                                : (const void*)lds_solve_kernel<5, kLdsSolveRows>)
-                                  : (short_band ? (const void*)lds_solve_kernel<9, kLdsSolveShortRows>
-                                                : (const void*)lds_solve_kernel<9, kLdsSolveRows>);
+    const int br = band <= kLdsSolveShortRows ? kLdsSolveShortRows
+                 : band <= kLdsSolveMidRows ? kLdsSolveMidRows : kLdsSolveRows;
+    const void* fn = nullptr;
+    if (stencil == 5)
+        fn = br == kLdsSolveShortRows ? (const void*)lds_solve_kernel<5, kLdsSolveShortRows>
+           : br == kLdsSolveMidRows ? (const void*)lds_solve_kernel<5, kLdsSolveMidRows>
+                                    : (const void*)lds_solve_kernel<5, kLdsSolveRows>;
+    else
+        fn = br == kLdsSolveShortRows ? (const void*)lds_solve_kernel<9, kLdsSolveShortRows>
+           : br == kLdsSolveMidRows ? (const void*)lds_solve_kernel<9, kLdsSolveMidRows>
+                                    : (const void*)lds_solve_kernel<9, kLdsSolveRows>;
     // the dynamic LDS limit is a property of the function on the current
     // device: set it at every launch (one host call per solve), so that every
     // device the library runs on gets it
@@ -1546,10 +1553,12 @@ hipError_t launch_lds_solve(int stencil, const Layout& L, double* A, const doubl
     hipLaunchKernelGGL((lds_solve_kernel<ST, BR>), dim3(1), dim3(kLdsSolveLanes), bytes, stream, A, G, w, M, \
                        L.nx, L.ny, L.pitch, wx, band, gnorm, tol, cycles_pred, max_cycles, out)
     if (stencil == 5) {
-        if (short_band) CJ_LDS_SOLVE(5, kLdsSolveShortRows);
+        if (br == kLdsSolveShortRows) CJ_LDS_SOLVE(5, kLdsSolveShortRows);
+        else if (br == kLdsSolveMidRows) CJ_LDS_SOLVE(5, kLdsSolveMidRows);
         else CJ_LDS_SOLVE(5, kLdsSolveRows);
     } else {
-        if (short_band) CJ_LDS_SOLVE(9, kLdsSolveShortRows);
+        if (br == kLdsSolveShortRows) CJ_LDS_SOLVE(9, kLdsSolveShortRows);
+        else if (br == kLdsSolveMidRows) CJ_LDS_SOLVE(9, kLdsSolveMidRows);
         else CJ_LDS_SOLVE(9, kLdsSolveRows);
     }
 #undef CJ_LDS_SOLVE

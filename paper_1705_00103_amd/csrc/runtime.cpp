@@ -66,9 +66,14 @@ int radius(int stencil) { return stencil == 17 ? 2 : 1; }
 // value of eps32 * kappa_max / kappa_min (CJ_INNER_AUTO).
 constexpr double kInnerF64Above = 4.0;
 
-// The single-workgroup solve is chosen automatically up to this many rows per
-// lane (the kernel's short-band variant, whose g stays in registers).
-constexpr int kLdsAutoRows = 4;
+// The single-workgroup solve is chosen automatically where it measured faster
+// than the launched cycles: bands of at most 4 rows per lane; of at most 8 for
+// the 5-point stencil, and for the 9-point one on grids of at most 4096 points
+// (its g stays in registers up to 8 rows).
+bool lds_auto(int stencil, int band, long long points) {
+    if (band <= 4) return true;
+    return band <= 8 && (stencil == 5 || points <= 4096);
+}
 
 }  // namespace
 
@@ -835,10 +840,10 @@ cj_status cj_plan_ex(int nx, int ny, int stencil, int bc, double tol, const cj_o
             return fail(CJ_ERR_ARG, "single_workgroup = 1 needs an FP64 5- or 9-point plan whose padded grid fits "
                                     "in LDS (at most 1024 columns, 16 rows per lane, 160 KiB)");
         }
-        // on by default only where one workgroup beat the launched cycles:
-        // bands of at most kLdsAutoRows rows per lane (one CU's FP64 and LDS
-        // rates fall behind the whole chip's beyond that)
-        p->use_lds = fits && (o.single_workgroup == 1 || (o.single_workgroup == 0 && band <= kLdsAutoRows));
+        // on by default only where one workgroup beat the launched cycles
+        // (one CU's FP64 and LDS rates fall behind the whole chip's beyond)
+        p->use_lds = fits && (o.single_workgroup == 1 ||
+                              (o.single_workgroup == 0 && lds_auto(stencil, band, (long long)nx * ny)));
     }
     {
         // graphs need whole K-launches per cycle with an even launch count

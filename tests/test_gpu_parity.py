@@ -335,7 +335,9 @@ SMALL = [(9, 128, 128, False, "chebyshev"), (5, 128, 128, False, "chebyshev"), (
          (9, 64, 256, True, "chebyshev"), (5, 70, 70, False, "jacobi"), (9, 130, 64, False, "chebyshev"),
          # bands of at most four rows: the variant that keeps g in registers
          (9, 32, 32, True, "chebyshev"), (5, 64, 64, False, "chebyshev"), (9, 256, 16, False, "jacobi"),
-         (5, 65, 61, False, "chebyshev")]
+         (5, 65, 61, False, "chebyshev"),
+         # bands of five to eight rows: the middle variant (g in registers)
+         (9, 96, 64, False, "chebyshev"), (9, 1000, 8, True, "chebyshev"), (5, 150, 40, False, "jacobi")]
 
 
 @pytest.mark.parametrize("st,nx,ny,frame,method", SMALL)
