@@ -228,6 +228,24 @@ def fp64_floor(f, n, ny, stencil):
             "dst_solution_relres_ext_eval": cjm.relative_residual_ext(stencil, f, u, np.zeros_like(u), n, ny)}
 
 
+def oracle_solution_check(f, u, u_lo, n, ny, stencil):
+    """The returned solution against the oracle (checker leg): its relative error
+    to the exact discrete solution (type-I sine transform, FP64) and the oracle's
+    relative residual of it, in FP64 and, for a double-double iterate u + u_lo,
+    in extended precision."""
+    import numpy as np
+    from oracle import cjm, dense
+    taps, s = cjm.taps(stencil)
+    exact = dense.dst_solve(taps, s, f, n, ny, cjm.spacing(n, ny))
+    lo = np.zeros_like(u) if u_lo is None else u_lo
+    err = float(np.linalg.norm((u - exact) + lo) / np.linalg.norm(exact))
+    out = {"rel_err_vs_exact_discrete": err,
+           "relres_oracle_fp64_eval": cjm.relative_residual(stencil, f, u, n, ny)}
+    if u_lo is not None:
+        out["relres_oracle_ext_eval"] = cjm.relative_residual_ext(stencil, f, u, lo, n, ny)
+    return out
+
+
 def run_batch(args):
     """Many independent problems: shapes log-uniform over [lo, hi] per axis (seeded),
     9-point stencil, 16-bump right-hand sides, one tolerance; one step = one
@@ -738,9 +756,15 @@ def main():
 
     cpu = None
     floor = None
+    check = None
     if not args.no_cpu_baseline and not mixed:
         cpu = cpu_baseline(n, ny, st, tol, seed, args.cpu_seconds, last["sweeps"])
         floor = fp64_floor(f, n, ny, st)
+    if not args.no_cpu_baseline and (mixed or dd):
+        # refinement and double-double runs: the last timed solve's result
+        # against the oracle (the checker's side of the line)
+        check = oracle_solution_check(f, u.cpu().numpy(), None if u_lo is None else u_lo.cpu().numpy(), n, ny,
+                                      st)
 
     # time to tolerance: the solve that meets tol (status ok) at the metric's
     # tolerance; the plain solve's time to its stagnation level is reported
@@ -783,6 +807,7 @@ def main():
         "sweeps_per_solve": last["sweeps"],
         "rel_residual": last["rel_residual"],
         "fp64_floor": floor,
+        "oracle_check": check,
         "roofline": roofline,
         "single_sweep_reference": single,
         "f64_reference": ref64,
