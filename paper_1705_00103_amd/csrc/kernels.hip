@@ -900,7 +900,10 @@ __global__ __launch_bounds__(256) void stage_out_kernel(const double* __restrict
 // the iterate has the same bits as the launched kernels; only the residual's
 // summation order differs.  Lane mapping: wave w covers columns
 // 1 + (w mod wx) * 64 + lane and the band w / wx of `band` rows; waves past
-// the last band only join the barriers.
+// the last band only join the barriers.  Three instantiations by the band
+// height BR they allow: up to 4 and up to 8 rows keep each lane's g in
+// registers for the whole solve; up to 16 rows read g again each sweep (L2),
+// which the 128-register budget of 1024-lane workgroups would otherwise spill.
 // out: [0] status (0 ok, 1 stagnated, -4 max cycles, -5 not finite),
 // [1] cycles, [2] last relative residual, [3] floor estimate.
 
