@@ -129,6 +129,37 @@ def test_blocked_sweeps_match_single_sweeps_bitwise(torch_cuda, st, K, nx, ny, r
     assert np.abs(_host(uk) - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("st", [5, 9])
+@pytest.mark.parametrize("frame", [False, True])
+@pytest.mark.parametrize("nx,ny,rows", [(985, 61, 16), (1476, 23, 0), (493, 40, 7)])
+def test_wide_strips_bitwise_at_their_seams(torch_cuda, st, frame, nx, ny, rows):
+    """K = 10 runs FP64 5- and 9-point sweeps in 512-lane strips (492 output
+    columns): widths of one strip plus a column, two strips plus one and three
+    strips, with homogeneous and frame data, give the bits of single sweeps and
+    the oracle's values."""
+    torch = torch_cuda
+    K, M = 10, 32
+    n = 2 * M + 3
+    f = inputs.gaussian_bumps_rhs(nx, ny, seed=23)
+    kw, obc = {}, cjm.BC_ZERO
+    if frame:
+        G = inputs.frame_width(st)
+        u0 = inputs.expxy_frame(nx, ny, G, interior=inputs.random_field(nx, ny, 24))
+        kw, obc = {"bc": cj.BC_FRAME}, cjm.BC_FRAME
+    else:
+        u0 = inputs.random_field(nx, ny, seed=24)
+    ref1 = _dev(torch, u0)
+    cj.sweeps(cj.plan(nx, ny, st, 1e-6, M=M, sweeps_per_launch=1, **kw), _dev(torch, f), ref1, n)
+    pk = cj.plan(nx, ny, st, 1e-6, M=M, sweeps_per_launch=K, tile_rows=rows, **kw)
+    k, r, wg = pk.refresh_launch_info()
+    assert k == K and wg == -(-nx // 492) * -(-ny // r)
+    uk = _dev(torch, u0)
+    cj.sweeps(pk, _dev(torch, f), uk, n)
+    assert np.array_equal(_host(uk), _host(ref1))
+    ref = cjm.run_sweeps(f, nx, ny, st, 1e-6, n, M=M, u0=u0, bc=obc)
+    assert np.abs(_host(uk) - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("st,K", [(9, 1), (9, 8), (9, 10), (5, 1), (17, 1), (17, 4)])
 def test_full_solve_parity_launch_depths(torch_cuda, st, K):
     torch = torch_cuda
