@@ -486,13 +486,14 @@ __device__ __forceinline__ void march_steps(March<T, ST, K>& S, T (*xch)[March<T
                                                        nx, ny, pitch, acc);
 }
 
+// Row-step blocks b0 .. b1 - 1 (a block is U row steps).
 template <typename T, int ST, int K, bool NORM, bool REFL, bool EDGE, bool EY>
 __device__ __forceinline__ void march(March<T, ST, K>& S, T (*xch)[March<T, ST, K>::W][March<T, ST, K>::SW],
                                       const T* __restrict__ uin, T* __restrict__ uout, const T* __restrict__ g,
-                                      const T (&om)[K], int ybase, int steps, int x, int xg, bool out_col, int Y0,
+                                      const T (&om)[K], int ybase, int b0, int b1, int x, int xg, bool out_col, int Y0,
                                       int Y1, int nx, int ny, int pitch, double& acc) {
     constexpr int U = March<T, ST, K>::U;
-    for (int t = 0; t < steps; t += U)
+    for (int t = b0 * U; t < b1 * U; t += U)
         march_steps<T, ST, K, NORM, REFL, EDGE, EY, 0>(S, xch, uin, uout, g, om, t, ybase, x, xg, out_col, Y0, Y1, nx,
                                                    ny, pitch, acc);
 }
@@ -558,17 +559,54 @@ __device__ __forceinline__ void sweepk_tile(const T* __restrict__ uin, T* __rest
     }
     double acc = 0.0;
     const int steps = (Y1 - Y0) + 2 * K * R + K - 1;
-    // three variants: interior; halo beyond the x-boundary only (with REFL,
-    // no closure of rows is needed); halo beyond a y-boundary
-    if (!edge_x && !edge_y)
-        march<T, ST, K, NORM, REFL, false, false>(S, xch, uin, uout, g, om, ybase, steps, x, xg, out_col, Y0, Y1, nx,
+    constexpr int U = MS::U;
+    const int nb = (steps + U - 1) / U;   // blocks of U row steps (rows past the tile are not stored)
+    if constexpr (REFL) {
+        // three variants: interior; halo beyond the x-boundary only (no
+        // closure of rows is needed); halo beyond a y-boundary
+        if (!edge_x && !edge_y)
+            march<T, ST, K, NORM, REFL, false, false>(S, xch, uin, uout, g, om, ybase, 0, nb, x, xg, out_col, Y0, Y1,
+                                                      nx, ny, pitch, acc);
+        else if (!edge_y)
+            march<T, ST, K, NORM, REFL, true, false>(S, xch, uin, uout, g, om, ybase, 0, nb, x, xg, out_col, Y0, Y1,
+                                                     nx, ny, pitch, acc);
+        else
+            march<T, ST, K, NORM, REFL, true, true>(S, xch, uin, uout, g, om, ybase, 0, nb, x, xg, out_col, Y0, Y1,
+                                                    nx, ny, pitch, acc);
+    } else {
+        // The outside nodes that an interior node reads are the columns 0 and
+        // nx + 1 and the rows 0 and ny + 1; every other outside node may take
+        // any value.  So the boundary selects run only in the wave that holds
+        // column 0 or nx + 1 (the others take the variant without selects: the
+        // choice is per wave, and every wave still meets one barrier per row
+        // step), and, where the halo reaches a y-boundary, only in the blocks
+        // that produce a row outside 1 .. ny at some level: level s produces
+        // row ybase + t - (s - 1) - sR in step t.  A selected node keeps the
+        // same value in every variant, so the variants give the same bits.
+        // The loops run one after another over (possibly empty) ranges of
+        // blocks; an alternative between two loops would make the compiler
+        // spill the register window where they join.
+        int bh = 0, bt = nb;   // blocks [0, bh) and [bt, nb) take the selects
+        if (__ballot(x == 0 || x == nx + 1) != 0) {
+            // The wave with the selects has the longest row step; at the
+            // default priority the older wave on its SIMD issues first, and the
+            // whole workgroup waits for the younger one at every barrier.
+            __builtin_amdgcn_s_setprio(2);
+            bt = 0;   // everything in the last loop, where fewer values are live
+        } else if (edge_y) {
+            const int lo = 1 - ybase + (K - 1) + K * R;      // first block whose lowest row is >= 1
+            bh = lo <= 0 ? 0 : min((lo + U - 1) / U, nb);
+            const int hi = ny - ybase - U + 1 + R;           // blocks b <= hi / U keep their rows <= ny
+            bt = hi < 0 ? 0 : min(hi / U + 1, nb);
+            bt = max(bt, bh);
+        }
+        march<T, ST, K, NORM, REFL, true, true>(S, xch, uin, uout, g, om, ybase, 0, bh, x, xg, out_col, Y0, Y1, nx, ny,
+                                                pitch, acc);
+        march<T, ST, K, NORM, REFL, false, false>(S, xch, uin, uout, g, om, ybase, bh, bt, x, xg, out_col, Y0, Y1, nx,
                                                   ny, pitch, acc);
-    else if (REFL && !edge_y)
-        march<T, ST, K, NORM, REFL, true, false>(S, xch, uin, uout, g, om, ybase, steps, x, xg, out_col, Y0, Y1, nx,
-                                                 ny, pitch, acc);
-    else
-        march<T, ST, K, NORM, REFL, true, true>(S, xch, uin, uout, g, om, ybase, steps, x, xg, out_col, Y0, Y1, nx,
-                                                ny, pitch, acc);
+        march<T, ST, K, NORM, REFL, true, true>(S, xch, uin, uout, g, om, ybase, bt, nb, x, xg, out_col, Y0, Y1, nx, ny,
+                                                pitch, acc);
+    }
     if (NORM) {
         const double tot = block_sum(acc);
         if (threadIdx.x == 0) part[tile] = tot;
