@@ -160,6 +160,49 @@ def test_wide_strips_bitwise_at_their_seams(torch_cuda, st, frame, nx, ny, rows)
     assert np.abs(_host(uk) - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+# (K, nx): the boundary column nx + 1 in the last lane of a wave, in the first
+# lane of the next one, and in the highest lane that can hold it (the last
+# output lane plus KR: lane 502 of 512, 248 of 256), for 512-lane (K = 10) and
+# 256-lane (K = 8) strips of FP64 5- and 9-point sweeps, in the first and in a
+# second strip; column 0 is lane KR - 1 of the first strip.
+WAVE_EDGE_CASES = [(10, 53), (10, 54), (10, 117), (10, 118), (10, 492),
+                   (8, 55), (8, 56), (8, 240), (8, 295), (8, 296)]
+
+
+@pytest.mark.parametrize("st", [5, 9])
+@pytest.mark.parametrize("frame", [False, True])
+@pytest.mark.parametrize("K,nx", WAVE_EDGE_CASES)
+def test_boundary_columns_at_wave_edges_bitwise(torch_cuda, st, frame, K, nx):
+    """Only the wave that holds column 0 or nx + 1 applies the column
+    boundary rule, and only the row blocks that reach a y-boundary apply the
+    row rule; with the boundary column at either side of a wave edge, and
+    tiles whose first and last row blocks touch the boundary rows, K blocked
+    sweeps still give the bits of K single sweeps and the oracle's values."""
+    torch = torch_cuda
+    M = 32
+    n = 2 * M + 3
+    ny, rows = (37, 16) if nx % 2 else (45, 0)
+    lanes = 512 if K >= 10 else 256
+    f = inputs.gaussian_bumps_rhs(nx, ny, seed=29)
+    kw, obc = {}, cjm.BC_ZERO
+    if frame:
+        G = inputs.frame_width(st)
+        u0 = inputs.expxy_frame(nx, ny, G, interior=inputs.random_field(nx, ny, 30))
+        kw, obc = {"bc": cj.BC_FRAME}, cjm.BC_FRAME
+    else:
+        u0 = inputs.random_field(nx, ny, seed=30)
+    ref1 = _dev(torch, u0)
+    cj.sweeps(cj.plan(nx, ny, st, 1e-6, M=M, sweeps_per_launch=1, **kw), _dev(torch, f), ref1, n)
+    pk = cj.plan(nx, ny, st, 1e-6, M=M, sweeps_per_launch=K, tile_rows=rows, **kw)
+    k, r, wg = pk.refresh_launch_info()
+    assert k == K and wg == -(-nx // (lanes - 2 * K)) * -(-ny // r)
+    uk = _dev(torch, u0)
+    cj.sweeps(pk, _dev(torch, f), uk, n)
+    assert np.array_equal(_host(uk), _host(ref1))
+    ref = cjm.run_sweeps(f, nx, ny, st, 1e-6, n, M=M, u0=u0, bc=obc)
+    assert np.abs(_host(uk) - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("st,K", [(9, 1), (9, 8), (9, 10), (5, 1), (17, 1), (17, 4)])
 def test_full_solve_parity_launch_depths(torch_cuda, st, K):
     torch = torch_cuda
