@@ -333,13 +333,14 @@ __global__ __launch_bounds__(256) void sweep_kernel(const T* __restrict__ uin, T
 // (256 - 2KR output columns) and the tiles overlap in y by KR rows.
 // The row loop is unrolled by a multiple of the window height W = 2R+1 (and
 // of the prefetch depth) so that the window rotation is a compile-time
-// renaming of registers.  Workgroups whose halo reaches the domain boundary
-// take a variant that closes the levels >= 1:
-// with REFL (17-point, homogeneous data) by the Dirichlet zeros and the odd
-// reflections of the level below; otherwise every node outside the interior
-// keeps, at every level, the value level 0 loaded for it (the boundary data).
-// Interior workgroups skip both, and with REFL a halo that crosses only an
-// x-boundary skips the closure of rows.  The closures are per-lane selects
+// renaming of registers.  Where the halo reaches the domain boundary a
+// variant closes the levels >= 1: with REFL (17-point, homogeneous data) by
+// the Dirichlet zeros and the odd reflections of the level below, in every
+// wave of the workgroup (a halo that crosses only an x-boundary skips the
+// closure of rows); otherwise the outside nodes that interior nodes read keep,
+// at every level, the value level 0 loaded for them (the boundary data), and
+// only the wave holding such a column and the row blocks reaching such a row
+// run that variant (see sweepk_tile).  Interior workgroups skip both.  The closures are per-lane selects
 // (select_lane), not branches: a branch would cut the row step into one
 // region per level and serialise the levels (edge workgroups took 1.4x as
 // long as interior ones at 8192^2, 9-point K = 10).
