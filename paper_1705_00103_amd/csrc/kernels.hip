@@ -473,8 +473,8 @@ __device__ __forceinline__ void march_step(March<T, ST, K>& S, T (*xch)[March<T,
     }
 }
 
-// Row steps t + J, t + J + 1, ..., t + U - 1 (compile-time phases).
-template <typename T, int ST, int K, bool NORM, bool REFL, bool EDGE, bool EY, int J>
+// Row steps t + J, t + J + 1, ..., t + UU - 1 (compile-time phases).
+template <typename T, int ST, int K, bool NORM, bool REFL, bool EDGE, bool EY, int J, int UU>
 __device__ __forceinline__ void march_steps(March<T, ST, K>& S, T (*xch)[March<T, ST, K>::W][March<T, ST, K>::SW],
                                             const T* __restrict__ uin, T* __restrict__ uout,
                                             const T* __restrict__ g, const T (&om)[K], int t, int ybase, int x,
@@ -482,20 +482,23 @@ __device__ __forceinline__ void march_steps(March<T, ST, K>& S, T (*xch)[March<T
                                             double& acc) {
     march_step<T, ST, K, NORM, REFL, EDGE, EY, J>(S, xch, uin, uout, g, om, t + J, ybase, x, xg, out_col, Y0, Y1, nx, ny,
                                               pitch, acc);
-    if constexpr (J + 1 < March<T, ST, K>::U)
-        march_steps<T, ST, K, NORM, REFL, EDGE, EY, J + 1>(S, xch, uin, uout, g, om, t, ybase, x, xg, out_col, Y0, Y1,
+    if constexpr (J + 1 < UU)
+        march_steps<T, ST, K, NORM, REFL, EDGE, EY, J + 1, UU>(S, xch, uin, uout, g, om, t, ybase, x, xg, out_col, Y0, Y1,
                                                        nx, ny, pitch, acc);
 }
 
-// Row-step blocks b0 .. b1 - 1 (a block is U row steps).
-template <typename T, int ST, int K, bool NORM, bool REFL, bool EDGE, bool EY>
+// Row-step blocks b0 .. b1 - 1 (a block is U row steps), UF blocks per pass
+// (b1 - b0 a multiple of UF).  At the end of a pass the registers the loop
+// carries wait for the loads and the store still in flight, so a longer pass
+// waits less often.
+template <typename T, int ST, int K, bool NORM, bool REFL, bool EDGE, bool EY, int UF = 1>
 __device__ __forceinline__ void march(March<T, ST, K>& S, T (*xch)[March<T, ST, K>::W][March<T, ST, K>::SW],
                                       const T* __restrict__ uin, T* __restrict__ uout, const T* __restrict__ g,
                                       const T (&om)[K], int ybase, int b0, int b1, int x, int xg, bool out_col, int Y0,
                                       int Y1, int nx, int ny, int pitch, double& acc) {
     constexpr int U = March<T, ST, K>::U;
-    for (int t = b0 * U; t < b1 * U; t += U)
-        march_steps<T, ST, K, NORM, REFL, EDGE, EY, 0>(S, xch, uin, uout, g, om, t, ybase, x, xg, out_col, Y0, Y1, nx,
+    for (int t = b0 * U; t < b1 * U; t += U * UF)
+        march_steps<T, ST, K, NORM, REFL, EDGE, EY, 0, U * UF>(S, xch, uin, uout, g, om, t, ybase, x, xg, out_col, Y0, Y1, nx,
                                                    ny, pitch, acc);
 }
 
@@ -601,10 +604,15 @@ __device__ __forceinline__ void sweepk_tile(const T* __restrict__ uin, T* __rest
             bt = hi < 0 ? 0 : min(hi / U + 1, nb);
             bt = max(bt, bh);
         }
+        // The loop without selects takes UF blocks per pass (12 row steps); a
+        // block left over runs in the last loop, whose selects keep every
+        // interior node's update.
+        constexpr int UF = sizeof(T) == 4 ? 4 : 2;
+        bt = bh + (bt - bh) / UF * UF;
         march<T, ST, K, NORM, REFL, true, true>(S, xch, uin, uout, g, om, ybase, 0, bh, x, xg, out_col, Y0, Y1, nx, ny,
                                                 pitch, acc);
-        march<T, ST, K, NORM, REFL, false, false>(S, xch, uin, uout, g, om, ybase, bh, bt, x, xg, out_col, Y0, Y1, nx,
-                                                  ny, pitch, acc);
+        march<T, ST, K, NORM, REFL, false, false, UF>(S, xch, uin, uout, g, om, ybase, bh, bt, x, xg, out_col, Y0, Y1,
+                                                      nx, ny, pitch, acc);
         march<T, ST, K, NORM, REFL, true, true>(S, xch, uin, uout, g, om, ybase, bt, nb, x, xg, out_col, Y0, Y1, nx, ny,
                                                 pitch, acc);
     }
