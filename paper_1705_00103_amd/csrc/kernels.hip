@@ -567,17 +567,29 @@ __device__ __forceinline__ void sweepk_tile(const T* __restrict__ uin, T* __rest
     constexpr int U = MS::U;
     const int nb = (steps + U - 1) / U;   // blocks of U row steps (rows past the tile are not stored)
     if constexpr (REFL) {
-        // three variants: interior; halo beyond the x-boundary only (no
-        // closure of rows is needed); halo beyond a y-boundary
-        if (!edge_x && !edge_y)
-            march<T, ST, K, NORM, REFL, false, false>(S, xch, uin, uout, g, om, ybase, 0, nb, x, xg, out_col, Y0, Y1,
-                                                      nx, ny, pitch, acc);
-        else if (!edge_y)
-            march<T, ST, K, NORM, REFL, true, false>(S, xch, uin, uout, g, om, ybase, 0, nb, x, xg, out_col, Y0, Y1,
-                                                     nx, ny, pitch, acc);
-        else
-            march<T, ST, K, NORM, REFL, true, true>(S, xch, uin, uout, g, om, ybase, 0, nb, x, xg, out_col, Y0, Y1,
-                                                    nx, ny, pitch, acc);
+        // The closure of rows runs only in the blocks where some level s >= 2
+        // reads a window row outside 1 .. ny (rows Y - R .. Y + R around the
+        // row Y that level s produces), the closure of columns in every wave of
+        // a workgroup whose halo crosses an x-boundary, and neither elsewhere.
+        // The loops run one after another over (possibly empty) ranges of
+        // blocks, as below.
+        int bh = 0, bt = nb;   // blocks [0, bh) and [bt, nb) close the rows
+        if (edge_y) {
+            const int lo = 1 + R - ybase + (K - 1) + K * R;  // first block whose lowest row is >= 1 + R
+            bh = lo <= 0 ? 0 : min((lo + U - 1) / U, nb);
+            const int hi = ny - R - ybase - U + 1 + R;       // blocks b <= hi / U keep their rows <= ny - R
+            bt = hi < 0 ? 0 : min(hi / U + 1, nb);
+            bt = max(bt, bh);
+        }
+        const int bm = edge_x ? bt : bh;   // columns closed in [bh, bm), nothing in [bm, bt)
+        march<T, ST, K, NORM, REFL, true, true>(S, xch, uin, uout, g, om, ybase, 0, bh, x, xg, out_col, Y0, Y1, nx, ny,
+                                                pitch, acc);
+        march<T, ST, K, NORM, REFL, true, false>(S, xch, uin, uout, g, om, ybase, bh, bm, x, xg, out_col, Y0, Y1, nx,
+                                                 ny, pitch, acc);
+        march<T, ST, K, NORM, REFL, false, false>(S, xch, uin, uout, g, om, ybase, bm, bt, x, xg, out_col, Y0, Y1, nx,
+                                                  ny, pitch, acc);
+        march<T, ST, K, NORM, REFL, true, true>(S, xch, uin, uout, g, om, ybase, bt, nb, x, xg, out_col, Y0, Y1, nx, ny,
+                                                pitch, acc);
     } else {
         // The outside nodes that an interior node reads are the columns 0 and
         // nx + 1 and the rows 0 and ny + 1; every other outside node may take
